@@ -1,0 +1,165 @@
+"""Test-side reference material written independently of the oracle and of
+the HIP library: textbook lattice tables, a Lagrange-multiplier minimisation
+of the entropy, and high-precision (mpmath) entropies."""
+from __future__ import annotations
+
+import itertools
+
+import mpmath as mp
+import numpy as np
+
+# Direction order of the C ABI: i = d(cx) + 3 d(cy) + 9 d(cz), d(0)=0, d(1)=1, d(-1)=2.
+_DIGIT = {0: 0, 1: 1, 2: -1}
+
+
+def abi_velocities(D: int) -> np.ndarray:
+    Q = 3 ** D
+    c = np.zeros((Q, 3), dtype=np.int64)
+    for i in range(Q):
+        rem = i
+        for a in range(D):
+            c[i, a] = _DIGIT[rem % 3]
+            rem //= 3
+    return c
+
+
+# Textbook weights: D1Q3 (2/3, 1/6, 1/6); D2Q9 rest 4/9, axis 1/9, diagonal 1/36;
+# D3Q27 rest 8/27, face 2/27, edge 1/54, corner 1/216.  Indexed by the number
+# of non-zero velocity components.
+TEXTBOOK_W = {1: {0: (2, 3), 1: (1, 6)},
+              2: {0: (4, 9), 1: (1, 9), 2: (1, 36)},
+              3: {0: (8, 27), 1: (2, 27), 2: (1, 54), 3: (1, 216)}}
+
+
+def textbook_weights(D: int) -> np.ndarray:
+    c = abi_velocities(D)
+    return np.array([TEXTBOOK_W[D][int(np.count_nonzero(ci))][0] /
+                     TEXTBOOK_W[D][int(np.count_nonzero(ci))][1] for ci in c])
+
+
+def lagrange_equilibrium(D: int, rho: float, u, iters: int = 60) -> np.ndarray:
+    """Minimise H(g) = sum g ln(g/W) subject to sum g = rho, sum c g = rho u by
+    Newton's method on the Lagrange multipliers: g_i = W_i exp(l0 + l.c_i)."""
+    c = abi_velocities(D)[:, :D].astype(np.float64)
+    W = textbook_weights(D)
+    A = np.hstack([np.ones((c.shape[0], 1)), c])  # [Q, D+1]
+    target = np.concatenate([[rho], rho * np.asarray(u[:D], dtype=np.float64)])
+    lam = np.zeros(D + 1)
+    lam[0] = np.log(rho)
+    for _ in range(iters):
+        g = W * np.exp(A @ lam)
+        r = A.T @ g - target
+        J = A.T @ (g[:, None] * A)
+        step = np.linalg.solve(J, r)
+        lam -= step
+        if np.max(np.abs(step)) < 1e-17:
+            break
+    return W * np.exp(A @ lam)
+
+
+def mp_lagrange_equilibrium(D: int, rho, u, dps: int = 50):
+    """Same minimisation in mpmath arithmetic (returns a list of mpf)."""
+    with mp.workdps(dps):
+        c = abi_velocities(D)[:, :D]
+        W = mp_weights(D)
+        rho = mp.mpf(rho)
+        uu = [mp.mpf(x) for x in u[:D]]
+        lam = [mp.log(rho)] + [mp.mpf(0)] * D
+        Q = len(c)
+        for _ in range(200):
+            g = [W[i] * mp.exp(lam[0] + sum(lam[a + 1] * int(c[i, a]) for a in range(D)))
+                 for i in range(Q)]
+            rows = [[mp.mpf(1)] + [mp.mpf(int(c[i, a])) for a in range(D)] for i in range(Q)]
+            r = [sum(g) - rho] + [sum(g[i] * rows[i][a + 1] for i in range(Q)) - rho * uu[a]
+                                  for a in range(D)]
+            J = mp.matrix(D + 1, D + 1)
+            for p in range(D + 1):
+                for q in range(D + 1):
+                    J[p, q] = sum(g[i] * rows[i][p] * rows[i][q] for i in range(Q))
+            step = mp.lu_solve(J, mp.matrix(r))
+            lam = [lam[k] - step[k] for k in range(D + 1)]
+            if max(abs(step[k]) for k in range(D + 1)) < mp.mpf(10) ** (-dps + 5):
+                break
+        return [W[i] * mp.exp(lam[0] + sum(lam[a + 1] * int(c[i, a]) for a in range(D)))
+                for i in range(Q)]
+
+
+def mp_weights(D: int):
+    c = abi_velocities(D)
+    out = []
+    for ci in c:
+        num, den = TEXTBOOK_W[D][int(np.count_nonzero(ci))]
+        out.append(mp.mpf(num) / mp.mpf(den))
+    return out
+
+
+def mp_H(f, W) -> mp.mpf:
+    """Eq. (3) in mpmath: sum f ln(f/W), 0 ln 0 = 0."""
+    h = mp.mpf(0)
+    for fi, wi in zip(f, W):
+        fi = mp.mpf(fi)
+        if fi < 0:
+            raise ValueError("negative population")
+        if fi > 0:
+            h += fi * mp.log(fi / wi)
+    return h
+
+
+def mp_G(D: int, f, alpha, dps: int = 50) -> mp.mpf:
+    """H(f + alpha (f^eq - f)) - H(f) with everything in mpmath: the
+    equilibrium from the multiplier minimisation, f taken exactly as given."""
+    with mp.workdps(dps):
+        fm = [mp.mpf(float(v)) for v in f]
+        rho = sum(fm)
+        c = abi_velocities(D)
+        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(D)]
+        feq = mp_lagrange_equilibrium(D, rho, u, dps)
+        W = mp_weights(D)
+        a = mp.mpf(float(alpha))
+        fs = [fm[i] + a * (feq[i] - fm[i]) for i in range(len(fm))]
+        # the component that defines alpha_max is zero up to the rounding of
+        # the double-precision alpha: read values of that size as zero
+        floor = -mp.mpf(1e-13) * max(fm)
+        fs = [max(v, mp.mpf(0)) if v > floor else v for v in fs]
+        return mp_H(fs, W) - mp_H(fm, W)
+
+
+def mp_root(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
+    """Nontrivial root of G on [lo, hi] by mpmath bisection (G(lo) <= 0 < G(hi))."""
+    with mp.workdps(dps):
+        fm = [mp.mpf(float(v)) for v in f]
+        rho = sum(fm)
+        c = abi_velocities(D)
+        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(D)]
+        feq = mp_lagrange_equilibrium(D, rho, u, dps)
+        W = mp_weights(D)
+        H0 = mp_H(fm, W)
+
+        def G(a):
+            fs = [fm[i] + a * (feq[i] - fm[i]) for i in range(len(fm))]
+            fs = [max(v, mp.mpf(0)) for v in fs]
+            return mp_H(fs, W) - H0
+
+        lo, hi = mp.mpf(lo), mp.mpf(hi)
+        for _ in range(iters):
+            mid = (lo + hi) / 2
+            if G(mid) > 0:
+                hi = mid
+            else:
+                lo = mid
+        return lo
+
+
+def near_equilibrium_state(D: int, rho: float, u, eps: float, rng, feq_fn) -> np.ndarray:
+    """f = f^eq (1 + eps xi) with xi projected so that f keeps the moments of
+    f^eq (feq_fn supplies the equilibrium; the projection uses only 1 and c)."""
+    c = abi_velocities(D)[:, :D].astype(np.float64)
+    feq = feq_fn(D, rho, u)
+    A = np.hstack([np.ones((c.shape[0], 1)), c])
+    xi = rng.standard_normal(c.shape[0])
+    # remove the part of feq*xi that changes the moments: solve A^T (feq xi - feq A m) = 0
+    M = A.T @ (feq[:, None] * A)
+    m = np.linalg.solve(M, A.T @ (feq * xi))
+    xi = xi - A @ m
+    xi /= np.max(np.abs(xi))
+    return feq * (1.0 + eps * xi)
