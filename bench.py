@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the ELBM hot path on one MI355X.
+
+Workload: D3Q27 entropic LBM Taylor-Green vortex, 512^3 periodic sites, FP32
+population storage, FP64 site arithmetic, u0 = 0.05, Re = 1600 (beta from
+nu = u0 L / Re, L = n / (2 pi)), closed-form alpha (Eqs. (8)-(9)).  One step
+= one launch of the fused pull-stream + collide kernel over the whole box,
+with the per-step counters (accepted alpha = 2, alpha range, mass, momentum)
+on.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line on stdout: MLUPS (value), the HBM roofline of the step
+kernel, the Newton-alpha and BGK comparisons on the same box, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--n 512]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline, closed-form vs Newton α; p50/p99 batched latency"
+HBM_PEAK_GBS = 8000.0
+BYTES = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1904_00866_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(workload_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_mode(elbm, torch, n, storage, beta, mode, steps, warmup, diag, rho, u):
+    sim = elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, device="cuda:0",
+                          storage=storage, beta=beta, mode=mode, diag=diag,
+                          root_max_iter=200)
+    stream = sim.stream
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = t0.elapsed_time(t1)
+    stats = sim.stats() if diag & elbm.DIAG_COUNTS else None
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return ms / steps, wall, stats
+
+
+def cpu_baseline(n_full, beta, budget_s=10.0):
+    """The FP64 oracle as it stands, OpenMP over sites, on a 128^3 sample of
+    the same Taylor-Green workload, for about budget_s seconds."""
+    import oracle
+    from paper_1904_00866_amd import workloads as Wk
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    m = 128
+    rho, u = Wk.taylor_green_3d(m)
+    cfg = oracle.Config(D=3, nx=m, ny=m, nz=m, beta=beta, nthreads=cores)
+    f = oracle.init(cfg, rho, u)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        f, _, _ = oracle.step(cfg, f)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    return {"value": round(m ** 3 * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"D3Q27 Taylor-Green {m}^3 (of the {n_full}^3 workload), closed-form "
+                      f"alpha, FP64, {steps} steps in {el:.1f} s on {cores} threads "
+                      f"({platform.processor() or platform.machine()})"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--storage", default="f32", choices=sorted(BYTES))
+    ap.add_argument("--compare-steps", type=int, default=10)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None, choices=["closed", "newton", "bisect", "bgk"],
+                    help="time one alpha mode only (profiling runs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU domain decomposition is a design, not a built path.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np  # noqa: F401
+    import torch
+
+    from paper_1904_00866_amd import elbm
+    from paper_1904_00866_amd import workloads as Wk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    elbm.lib()
+    n, storage = args.n, args.storage
+    N = n ** 3
+    beta = Wk.tgv3d_beta(n)
+    log(f"building {n}^3 Taylor-Green fields")
+    rho, u = Wk.taylor_green_3d(n)
+    diag = elbm.DIAG_COUNTS
+    results = {}
+    modes = [args.only] if args.only else (["closed"] if args.no_compare
+                                           else ["closed", "bgk", "newton"])
+    for mode in modes:
+        steps = args.steps if mode in ("closed", "bgk") else args.compare_steps
+        warm = args.warmup if mode in ("closed", "bgk") else 2
+        log(f"{mode}: warmup {warm}, timing {steps} steps")
+        ms, wall, st = time_mode(elbm, torch, n, storage, beta, mode, steps, warm, diag, rho, u)
+        results[mode] = dict(ms=ms, wall=wall, stats=st, steps=steps)
+        log(f"{mode}: {ms:.3f} ms/step, {N / ms / 1e3:.0f} MLUPS")
+    del rho, u
+
+    main_mode = args.only or "closed"
+    r = results[main_mode]
+    ms = r["ms"]
+    mlups = N / (ms * 1e-3) / 1e6
+    Q, b = 27, BYTES[storage]
+    alg_bytes = 2 * Q * b * N  # read + write every population once per step
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    key = f"d3q27_{n}_{storage}_{main_mode}"
+    traffic = measured_traffic(key)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": r["steps"],
+        "warmup": args.warmup if main_mode in ("closed", "bgk") else 2,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (analytic Taylor-Green initial field)",
+        "config": {"workload": f"D3Q27 ELBM Taylor-Green vortex {n}^3 periodic, "
+                               f"{storage.upper()} population storage, FP64 site arithmetic, "
+                               f"u0=0.05, Re=1600, {main_mode} alpha",
+                   "lattice": "D3Q27", "n": n, "sites": N, "storage": storage,
+                   "beta": beta, "alpha_mode": main_mode, "diagnostics": "counts"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "kernel": f"k_step<3,Store{storage},{main_mode}>"},
+    }
+    st = r["stats"]
+    if st:
+        out["diagnostics"] = {"accept2_fraction": round(st["n_accept2"] / N, 4),
+                              "alpha_lt2_fraction": round(st["n_alpha_lt2"] / N, 4),
+                              "alpha_min": st["alpha_min"],
+                              "negative_populations": st["n_negative"],
+                              "nonfinite_populations": st["n_nonfinite"]}
+    if "newton" in results or "bgk" in results:
+        cmp = {}
+        if "newton" in results:
+            cmp["newton_mlups"] = round(N / results["newton"]["ms"] / 1e3, 1)
+            cmp["closed_over_newton"] = round(results["newton"]["ms"] / ms, 2)
+            stn = results["newton"]["stats"]
+            if stn:
+                cmp["newton_iters_per_site"] = round(stn["total_iters"] / N, 3)
+        if "bgk" in results:
+            cmp["bgk_mlups"] = round(N / results["bgk"]["ms"] / 1e3, 1)
+            cmp["closed_over_bgk_time"] = round(ms / results["bgk"]["ms"], 3)
+        out["comparison"] = cmp
+    if not args.no_cpu_baseline and not args.only:
+        log("CPU oracle baseline (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(n, beta)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

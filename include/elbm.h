@@ -1,0 +1,209 @@
+/*
+ * elbm.h -- C ABI of the MI355X (gfx950) entropic lattice Boltzmann library.
+ *
+ * The library advances the entropic lattice Boltzmann method (ELBM) of
+ * Zhao & Yong, "Relaxation-rate formula for the entropic lattice Boltzmann
+ * method": per time step and lattice site it
+ *   1. pulls the streamed populations f_i(x,t) (Eq. (5b)),
+ *   2. forms rho = sum_i f_i and rho u = sum_i c_i f_i (the conservation
+ *      constraints stated after Eq. (3)),
+ *   3. builds the entropic equilibrium f^eq, the minimiser of
+ *      H(f) = sum_i f_i ln(f_i/W_i) (Eq. (3)) under those constraints,
+ *   4. chooses alpha: alpha_max (definition after Eq. (7)), alpha_* = min(2,
+ *      alpha_max) (Eq. (8)), alpha = alpha_* if H(f*(alpha_*)) <= H(f),
+ *      otherwise the closed form Eq. (9),
+ *   5. collides, f~_i = f_i + alpha beta (f_i^eq - f_i) (Eq. (1) = Eq. (5a)),
+ *      and stores f~ for the next step's pull.
+ * Beside it: the entropy balance Eq. (4) solved per site by Newton or by
+ * bisection (stop window -tol <= H(f*) - H(f) <= 0 as in the double-shear
+ * comparison), the modified secant iteration of the closing remark, and
+ * LBGK (alpha = 2, polynomial equilibrium; the special case after Eq. (4)).
+ *
+ * Conventions
+ *   - Lattice units: delta_x = delta_t = 1, c_s^2 = 1/3, so Eq. (2) reads
+ *     beta = 1 / (6 nu + 1).  Periodic box nx * ny * nz (ny = nz = 1 for
+ *     D1Q3, nz = 1 for D2Q9), N = nx*ny*nz sites, site index
+ *     s = x + nx*(y + ny*z).
+ *   - Directions: c_i in {-1,0,1}^D with i = d(c_x) + 3 d(c_y) + 9 d(c_z),
+ *     d(0) = 0, d(+1) = 1, d(-1) = 2.  Weights W_i = prod_a w(c_ia),
+ *     w(0) = 2/3, w(+-1) = 1/6 (D2Q9: 4/9, 1/9, 1/36).
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd or a torch
+ *     tensor's data pointer) unless its comment says "host".  Population
+ *     arrays are SoA float64: f[i*N + s]; velocity arrays are SoA u[a*N + s].
+ *   - f(x,t) always means the paper's pre-collision populations at time t.
+ *
+ * Memory and streams
+ *   - The caller owns all device memory.  elbm_init places the whole
+ *     simulation state (two population buffers, the optional alpha field and
+ *     the diagnostics area) in the caller's buffer of elbm_state_bytes()
+ *     bytes, which must stay allocated and untouched until elbm_destroy.
+ *     The library itself calls no hipMalloc; it allocates only the small
+ *     host-side handle.
+ *   - Every call enqueues work on the stream given to elbm_init and returns
+ *     without waiting, except where its comment says it synchronises.
+ *   - A handle may be used from one host thread at a time.
+ *
+ * Errors
+ *   - Every function returns an elbm_status; nothing is thrown across the
+ *     ABI.  elbm_last_error() returns a message for the calling thread's
+ *     last failure.  Numerical events (negative or non-finite populations)
+ *     are not errors: they are counted in elbm_stats.
+ */
+#ifndef ELBM_H
+#define ELBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ELBM_ABI_VERSION 1
+
+typedef struct elbm_sim elbm_sim; /* opaque; owned by the library */
+
+typedef enum {
+  ELBM_OK = 0,
+  ELBM_EINVAL = -1,      /* invalid argument or configuration            */
+  ELBM_EDEVICE = -2,     /* a HIP runtime call failed                    */
+  ELBM_ENOMEM = -3,      /* caller buffer smaller than elbm_state_bytes  */
+  ELBM_ESTATE = -4,      /* call not valid in the handle's current state */
+  ELBM_EUNSUPPORTED = -5 /* combination not built into this library      */
+} elbm_status;
+
+enum { ELBM_D1Q3 = 1, ELBM_D2Q9 = 2, ELBM_D3Q27 = 3 };
+
+enum {
+  ELBM_ALPHA_CLOSED = 0, /* Eq. (8), acceptance test, Eq. (9)            */
+  ELBM_ALPHA_NEWTON = 1, /* bracketed Newton root of Eq. (4)             */
+  ELBM_ALPHA_BISECT = 2, /* bisection root of Eq. (4), window root_tol   */
+  ELBM_ALPHA_BGK = 3,    /* alpha = 2 with the polynomial equilibrium    */
+  ELBM_ALPHA_SECANT = 4  /* modified secant, secant_iters iterations     */
+};
+
+/* Population storage.  *_DEV stores s_i = f_i / W_i - rho_ref ("deviation
+ * from W_i rho"), decoded as f_i = W_i (rho_ref + s_i); FP16 is rounded to
+ * nearest even. */
+enum {
+  ELBM_STORE_F64 = 0,
+  ELBM_STORE_F32 = 1,
+  ELBM_STORE_F32_DEV = 2,
+  ELBM_STORE_F16_DEV = 3
+};
+
+/* Diagnostics switches (bit mask). */
+enum {
+  ELBM_DIAG_ALPHA = 1u,  /* record alpha(x) of every step (8 B/site extra) */
+  ELBM_DIAG_COUNTS = 2u, /* per-step counts, alpha range, mass, momentum  */
+  ELBM_DIAG_ENTROPY = 4u /* also sum_x H(f(x,t)) (Eq. (6)); needs COUNTS  */
+};
+
+typedef struct {
+  int32_t lattice;       /* ELBM_D1Q3 / ELBM_D2Q9 / ELBM_D3Q27            */
+  int32_t nx, ny, nz;    /* box, each >= 1                                */
+  double beta;           /* Eq. (2), 0 < beta < 1                         */
+  int32_t alpha_mode;    /* ELBM_ALPHA_*                                  */
+  int32_t storage;       /* ELBM_STORE_*                                  */
+  int32_t alpha_fp64;    /* 1: site arithmetic in FP64 (required for
+                            STORE_F64); 0: FP32 arithmetic (closed mode,
+                            FP32/FP16 storage only)                       */
+  int32_t secant_iters;  /* iterations of ELBM_ALPHA_SECANT (>= 1)        */
+  double rho_ref;        /* reference density of *_DEV storage (> 0)      */
+  double root_tol;       /* bisection window; the paper uses 1e-13        */
+  int32_t root_max_iter; /* cap for Newton / bisection iterations (>= 1)  */
+  uint32_t diag;         /* ELBM_DIAG_* mask                              */
+  int32_t plane_pad;     /* extra elements between population planes;
+                            -1 selects the library default                */
+  int32_t reserved;
+} elbm_config;
+
+/* Per-step diagnostics of the most recent step (ELBM_DIAG_COUNTS).  In
+ * ELBM_ALPHA_BGK mode the entropic alpha rules are not evaluated, so the
+ * alpha-rule counts (n_accept2 ... n_fallback, total_iters) stay 0. */
+typedef struct {
+  int64_t step;            /* t after the step that produced these         */
+  int64_t n_sites;
+  int64_t n_accept2;       /* sites with H(f*(2)) <= H(f) (Fig. 5's count) */
+  int64_t n_alphastar_lt2; /* sites with alpha_max < 2                     */
+  int64_t n_alpha_lt2;     /* sites with alpha < 2                         */
+  int64_t n_guard;         /* sites with f = f^eq to rounding              */
+  int64_t n_fallback;      /* sites evaluated with log1p, not the series   */
+  int64_t n_negative;      /* post-collision populations < 0               */
+  int64_t n_nonfinite;     /* post-collision populations NaN or inf        */
+  int64_t total_iters;     /* root-solver / secant iterations, summed      */
+  double alpha_min, alpha_max;
+  double sum_rho;          /* sum_x rho(x,t)                               */
+  double sum_j[3];         /* sum_x rho u(x,t)                             */
+  double sum_H;            /* sum_x H(f(x,t)) if ELBM_DIAG_ENTROPY, else 0 */
+} elbm_stats_t;
+
+/* Default configuration for a lattice and box (closed-form alpha, FP32
+ * storage, FP64 site arithmetic, beta = 0.95, root_tol = 1e-13, no
+ * diagnostics). */
+elbm_status elbm_config_default(elbm_config *cfg, int32_t lattice, int32_t nx,
+                                int32_t ny, int32_t nz);
+
+/* Bytes of device memory the simulation state needs (0 on invalid cfg). */
+size_t elbm_state_bytes(const elbm_config *cfg);
+
+/* Create a simulation in the caller's device buffer dev_state (>= bytes of
+ * elbm_state_bytes, 256-byte aligned) and set f(x,0) = f^eq(rho0(x), u0(x))
+ * with rho0[N] > 0 and u0[D*N], |u0| < 1 per component (the domain of the
+ * entropic equilibrium).  hip_stream is a hipStream_t (NULL = the null
+ * stream).  Synchronises the stream once to validate rho0 and u0; returns
+ * ELBM_EINVAL if any value is out of range.  *out receives the handle. */
+elbm_status elbm_init(const elbm_config *cfg, const double *rho0,
+                      const double *u0, void *dev_state, size_t bytes,
+                      void *hip_stream, elbm_sim **out);
+
+/* Overwrite the state with arbitrary pre-collision populations f(x,t),
+ * f[Q*N] float64 (non-negative for the entropic modes).  t is unchanged. */
+elbm_status elbm_set_populations(elbm_sim *sim, const double *f);
+
+/* Advance nsteps >= 0 time steps (Eq. (1) then Eq. (5b) per step). */
+elbm_status elbm_step(elbm_sim *sim, int64_t nsteps);
+
+/* rho[N] and u[D*N] of the current f(x,t) (float64). */
+elbm_status elbm_moments(elbm_sim *sim, double *rho, double *u);
+
+/* Current pre-collision populations f(x,t) as float64 f[Q*N]. */
+elbm_status elbm_populations(elbm_sim *sim, double *f);
+
+/* Gather at n sites (site indices sites[n], int64, device):
+ *   which = 0: the pre-collision f(x,t) of those sites;
+ *   which = 1: the post-collision f~(x,t-1) the last step wrote there.
+ * out[i*n + k] (float64). */
+elbm_status elbm_gather(elbm_sim *sim, const int64_t *sites, int64_t n,
+                        int32_t which, double *out);
+
+/* alpha(x) used by the most recent step (requires ELBM_DIAG_ALPHA and at
+ * least one step), copied into alpha[N] (float64). */
+elbm_status elbm_alpha_field(elbm_sim *sim, double *alpha);
+
+/* Diagnostics of the most recent step (requires ELBM_DIAG_COUNTS and at
+ * least one step).  stats is a HOST pointer; synchronises the stream. */
+elbm_status elbm_stats(elbm_sim *sim, elbm_stats_t *stats);
+
+/* Time t of the current state (host value, no synchronisation). */
+int64_t elbm_time(const elbm_sim *sim);
+
+/* Release the handle (not the caller's device buffer).  Waits for the
+ * handle's pending work first. */
+elbm_status elbm_destroy(elbm_sim *sim);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *elbm_last_error(void);
+
+/* Advance several independent simulations that share one stream with ONE
+ * kernel launch per step: sims[n] all created on the same stream with the
+ * same lattice, storage, alpha mode and arithmetic; nsteps[n] (host) steps
+ * each, sims with fewer steps drop out as they finish.  Results are
+ * identical to stepping each simulation alone. */
+elbm_status elbm_step_batch(elbm_sim *const *sims, const int64_t *nsteps,
+                            int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELBM_H */

@@ -1,0 +1,483 @@
+// elbm_api.cpp -- host runtime of the ELBM library: configuration checks,
+// placement of the state in the caller's device buffer, launch set-up,
+// stream handling and error reporting behind the C ABI of include/elbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/elbm.h"
+#include "elbm_internal.hpp"
+
+using namespace elbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+elbm_status fail(elbm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+elbm_status hip_fail(hipError_t e, const char* what) {
+  return fail(ELBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxDim = (1 << 20) - 1;  // site-coordinate arithmetic limit
+constexpr int64_t kMaxSites = (int64_t(1) << 31) - 1;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int elem_size(int storage) {
+  switch (storage) {
+    case ELBM_STORE_F64: return 8;
+    case ELBM_STORE_F32: return 4;
+    case ELBM_STORE_F32_DEV: return 4;
+    case ELBM_STORE_F16_DEV: return 2;
+    default: return 0;
+  }
+}
+
+struct Layout {
+  int D, Q, esize;
+  int64_t N, pitch;
+  int nblocks;
+  size_t off_buf[2], off_alpha, off_partials, off_misc, total;
+};
+
+elbm_status check_config(const elbm_config* c, Layout* L) {
+  if (!c) return fail(ELBM_EINVAL, "config is NULL");
+  if (c->lattice < ELBM_D1Q3 || c->lattice > ELBM_D3Q27)
+    return fail(ELBM_EINVAL, "unknown lattice %d", c->lattice);
+  const int D = c->lattice;
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1)
+    return fail(ELBM_EINVAL, "box %d x %d x %d: every extent must be >= 1", c->nx, c->ny, c->nz);
+  if (c->nx > kMaxDim || c->ny > kMaxDim || c->nz > kMaxDim)
+    return fail(ELBM_EINVAL, "box extent above %lld", (long long)kMaxDim);
+  if (D == 1 && (c->ny != 1 || c->nz != 1)) return fail(ELBM_EINVAL, "D1Q3 needs ny = nz = 1");
+  if (D == 2 && c->nz != 1) return fail(ELBM_EINVAL, "D2Q9 needs nz = 1");
+  const int64_t N = int64_t(c->nx) * c->ny * c->nz;
+  if (N > kMaxSites) return fail(ELBM_EINVAL, "%lld sites exceed %lld", (long long)N, (long long)kMaxSites);
+  if (!(c->beta > 0.0 && c->beta < 1.0))
+    return fail(ELBM_EINVAL, "beta = %g outside (0, 1) (Eq. (2))", c->beta);
+  if (c->alpha_mode < ELBM_ALPHA_CLOSED || c->alpha_mode > ELBM_ALPHA_SECANT)
+    return fail(ELBM_EINVAL, "unknown alpha mode %d", c->alpha_mode);
+  const int es = elem_size(c->storage);
+  if (!es) return fail(ELBM_EINVAL, "unknown storage %d", c->storage);
+  if (c->alpha_fp64 != 0 && c->alpha_fp64 != 1) return fail(ELBM_EINVAL, "alpha_fp64 must be 0 or 1");
+  if (!c->alpha_fp64 && c->storage == ELBM_STORE_F64)
+    return fail(ELBM_EUNSUPPORTED, "FP64 storage needs FP64 arithmetic");
+  if (!c->alpha_fp64 && c->alpha_mode != ELBM_ALPHA_CLOSED)
+    return fail(ELBM_EUNSUPPORTED, "FP32 arithmetic is built for the closed-form alpha only");
+  if ((c->storage == ELBM_STORE_F32_DEV || c->storage == ELBM_STORE_F16_DEV) &&
+      !(c->rho_ref > 0.0 && std::isfinite(c->rho_ref)))
+    return fail(ELBM_EINVAL, "rho_ref must be > 0 for deviation storage");
+  if (c->alpha_mode == ELBM_ALPHA_SECANT && c->secant_iters < 1)
+    return fail(ELBM_EINVAL, "secant_iters must be >= 1");
+  if ((c->alpha_mode == ELBM_ALPHA_NEWTON || c->alpha_mode == ELBM_ALPHA_BISECT) &&
+      c->root_max_iter < 1)
+    return fail(ELBM_EINVAL, "root_max_iter must be >= 1");
+  if (c->alpha_mode == ELBM_ALPHA_BISECT && !(c->root_tol >= 0.0))
+    return fail(ELBM_EINVAL, "root_tol must be >= 0");
+  if (c->diag & ~7u) return fail(ELBM_EINVAL, "unknown diagnostics bits 0x%x", c->diag);
+  if ((c->diag & ELBM_DIAG_ENTROPY) && !(c->diag & ELBM_DIAG_COUNTS))
+    return fail(ELBM_EINVAL, "ELBM_DIAG_ENTROPY needs ELBM_DIAG_COUNTS");
+  if (c->plane_pad < -1) return fail(ELBM_EINVAL, "plane_pad must be >= -1");
+  if (!step_launcher(D, c->storage, c->alpha_mode, c->alpha_fp64))
+    return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
+
+  L->D = D;
+  L->Q = D == 1 ? 3 : D == 2 ? 9 : 27;
+  L->esize = es;
+  L->N = N;
+  // Planes start on 256-byte boundaries; the default adds one 256-byte
+  // block so that equal sites of different planes are not a multiple of a
+  // large power of two apart.
+  const int64_t per256 = 256 / es;
+  const int64_t pad = c->plane_pad >= 0 ? c->plane_pad : per256;
+  L->pitch = int64_t(align_up(size_t(N + pad), size_t(per256)));
+  // The kernels address a plane with 32-bit byte offsets.
+  if (uint64_t(L->pitch) * uint64_t(es) >= (uint64_t(1) << 32))
+    return fail(ELBM_EINVAL, "%lld sites of %d bytes exceed the 4 GiB plane limit",
+                (long long)N, es);
+  // One workgroup per tile of kBlock sites, rounded up to a multiple of 8
+  // (the kernel's XCD-aware tile order needs it).
+  const int64_t ntiles = (N + kBlock - 1) / kBlock;
+  L->nblocks = int((ntiles + 7) / 8 * 8);
+  size_t off = 0;
+  const size_t bufbytes = align_up(size_t(L->Q) * size_t(L->pitch) * es, kAlign);
+  L->off_buf[0] = off;
+  off += bufbytes;
+  L->off_buf[1] = off;
+  off += bufbytes;
+  L->off_alpha = off;
+  if (c->diag & ELBM_DIAG_ALPHA) off += align_up(size_t(N) * 8, kAlign);
+  L->off_partials = off;
+  if (c->diag & ELBM_DIAG_COUNTS) off += align_up(size_t(L->nblocks) * kPartialBytes, kAlign);
+  L->off_misc = off;
+  off += align_up(sizeof(Reduced) + 64, kAlign);
+  L->total = off;
+  return ELBM_OK;
+}
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct elbm_sim {
+  elbm_config cfg;
+  Layout L;
+  char* base;
+  void* buf[2];
+  int cur;  // buffer holding the state that the next step reads
+  double* alpha;
+  void* partials;
+  Reduced* reduced;
+  unsigned long long* counter;
+  hipStream_t stream;
+  int device;
+  int64_t t;
+  bool have_alpha, have_stats;
+  StepLauncher launch;
+};
+
+namespace {
+
+BoxDesc box_of(const elbm_sim* s) {
+  BoxDesc b;
+  b.D = s->L.D;
+  b.storage = s->cfg.storage;
+  b.nx = s->cfg.nx;
+  b.ny = s->cfg.ny;
+  b.nz = s->cfg.nz;
+  b.N = s->L.N;
+  b.pitch = s->L.pitch;
+  b.rho_ref = s->cfg.rho_ref;
+  return b;
+}
+
+SimDesc desc_of(const elbm_sim* s, int block_begin) {
+  SimDesc d;
+  std::memset(&d, 0, sizeof d);
+  d.src = s->buf[s->cur];
+  d.dst = s->buf[1 - s->cur];
+  d.alpha = (s->cfg.diag & ELBM_DIAG_ALPHA) ? s->alpha : nullptr;
+  d.partials = (s->cfg.diag & ELBM_DIAG_COUNTS) ? s->partials : nullptr;
+  d.pitch = s->L.pitch;
+  d.beta = s->cfg.beta;
+  d.rho_ref = s->cfg.rho_ref;
+  d.root_tol = s->cfg.root_tol;
+  d.nx = s->cfg.nx;
+  d.ny = s->cfg.ny;
+  d.nz = s->cfg.nz;
+  d.rows = s->cfg.ny * s->cfg.nz;
+  d.nblocks = s->L.nblocks;
+  d.block_begin = block_begin;
+  d.root_max_iter = s->cfg.root_max_iter;
+  d.secant_iters = s->cfg.secant_iters;
+  d.diag = int(s->cfg.diag);
+  return d;
+}
+
+void after_step(elbm_sim* s) {
+  s->cur = 1 - s->cur;
+  s->t += 1;
+  if (s->cfg.diag & ELBM_DIAG_ALPHA) s->have_alpha = true;
+  if (s->cfg.diag & ELBM_DIAG_COUNTS) s->have_stats = true;
+}
+
+elbm_status check_sim(const elbm_sim* s) {
+  if (!s) return fail(ELBM_EINVAL, "simulation handle is NULL");
+  return ELBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elbm_status elbm_config_default(elbm_config* c, int32_t lattice, int32_t nx, int32_t ny,
+                                int32_t nz) {
+  if (!c) return fail(ELBM_EINVAL, "config is NULL");
+  std::memset(c, 0, sizeof *c);
+  c->lattice = lattice;
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->beta = 0.95;
+  c->alpha_mode = ELBM_ALPHA_CLOSED;
+  c->storage = ELBM_STORE_F32;
+  c->alpha_fp64 = 1;
+  c->secant_iters = 3;
+  c->rho_ref = 1.0;
+  c->root_tol = 1e-13;
+  c->root_max_iter = 200;
+  c->diag = 0;
+  c->plane_pad = -1;
+  return ELBM_OK;
+}
+
+size_t elbm_state_bytes(const elbm_config* cfg) {
+  Layout L;
+  if (check_config(cfg, &L) != ELBM_OK) return 0;
+  return L.total;
+}
+
+elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* u0,
+                      void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out) {
+  if (!out) return fail(ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  elbm_status st = check_config(cfg, &L);
+  if (st != ELBM_OK) return st;
+  if (!dev_state) return fail(ELBM_EINVAL, "dev_state is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_state) % kAlign)
+    return fail(ELBM_EINVAL, "dev_state must be %zu-byte aligned", kAlign);
+  if (bytes < L.total)
+    return fail(ELBM_ENOMEM, "state buffer of %zu bytes, %zu needed", bytes, L.total);
+  if (!rho0 || !u0) return fail(ELBM_EINVAL, "rho0 / u0 is NULL");
+
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  elbm_sim* s = new (std::nothrow) elbm_sim;
+  if (!s) return fail(ELBM_EINVAL, "out of host memory");
+  s->cfg = *cfg;
+  s->L = L;
+  s->base = static_cast<char*>(dev_state);
+  s->buf[0] = s->base + L.off_buf[0];
+  s->buf[1] = s->base + L.off_buf[1];
+  s->cur = 0;
+  s->alpha = reinterpret_cast<double*>(s->base + L.off_alpha);
+  s->partials = s->base + L.off_partials;
+  s->reduced = reinterpret_cast<Reduced*>(s->base + L.off_misc);
+  s->counter = reinterpret_cast<unsigned long long*>(s->base + L.off_misc + sizeof(Reduced));
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->device = dev;
+  s->t = 0;
+  s->have_alpha = s->have_stats = false;
+  s->launch = step_launcher(L.D, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64);
+
+  const BoxDesc b = box_of(s);
+  unsigned long long nbad = 0;
+  if ((e = hipMemsetAsync(s->counter, 0, sizeof(unsigned long long), s->stream)) != hipSuccess ||
+      (e = launch_validate_init(b, rho0, u0, s->counter, s->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(&nbad, s->counter, sizeof nbad, hipMemcpyDeviceToHost, s->stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s->stream)) != hipSuccess) {
+    delete s;
+    return hip_fail(e, "elbm_init validation");
+  }
+  if (nbad) {
+    delete s;
+    return fail(ELBM_EINVAL,
+                "%llu sites with rho0 <= 0 or |u0| >= 1 (outside the entropic equilibrium's domain)",
+                nbad);
+  }
+  // Zero both buffers' padding once so that every byte of the state is
+  // defined, then place f^eq(rho0, u0) in pull convention.
+  if ((e = hipMemsetAsync(s->base, 0, L.off_alpha, s->stream)) != hipSuccess ||
+      (e = launch_scatter(b, s->buf[0], rho0, u0, nullptr, 0, s->stream)) != hipSuccess) {
+    delete s;
+    return hip_fail(e, "elbm_init");
+  }
+  *out = s;
+  return ELBM_OK;
+}
+
+elbm_status elbm_set_populations(elbm_sim* s, const double* f) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (!f) return fail(ELBM_EINVAL, "f is NULL");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  hipError_t e = launch_scatter(box_of(s), s->buf[s->cur], nullptr, nullptr, f, 1, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "elbm_set_populations");
+  s->have_alpha = s->have_stats = false;
+  return ELBM_OK;
+}
+
+elbm_status elbm_step(elbm_sim* s, int64_t nsteps) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (nsteps < 0) return fail(ELBM_EINVAL, "nsteps < 0");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  BatchArgs a;
+  a.n = 1;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    a.d[0] = desc_of(s, 0);
+    hipError_t e = s->launch(a, s->L.nblocks, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    after_step(s);
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_step_batch(elbm_sim* const* sims, const int64_t* nsteps, int32_t n) {
+  if (n < 0 || (n > 0 && (!sims || !nsteps))) return fail(ELBM_EINVAL, "bad batch arguments");
+  if (n == 0) return ELBM_OK;
+  const elbm_sim* s0 = sims[0];
+  int64_t kmax = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const elbm_sim* s = sims[k];
+    if (!s) return fail(ELBM_EINVAL, "batch entry %d is NULL", k);
+    if (nsteps[k] < 0) return fail(ELBM_EINVAL, "batch entry %d: nsteps < 0", k);
+    if (s->L.D != s0->L.D || s->cfg.storage != s0->cfg.storage ||
+        s->cfg.alpha_mode != s0->cfg.alpha_mode || s->cfg.alpha_fp64 != s0->cfg.alpha_fp64)
+      return fail(ELBM_EINVAL, "batch entry %d: lattice/storage/mode/precision differ", k);
+    if (s->stream != s0->stream || s->device != s0->device)
+      return fail(ELBM_EINVAL, "batch entry %d: different stream or device", k);
+    for (int32_t m = 0; m < k; ++m)
+      if (sims[m] == s) return fail(ELBM_EINVAL, "batch entry %d repeats entry %d", k, m);
+    if (nsteps[k] > kmax) kmax = nsteps[k];
+  }
+  DeviceGuard g(s0->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulations' device");
+  std::vector<elbm_sim*> active;
+  active.reserve(size_t(n));
+  for (int64_t step = 0; step < kmax; ++step) {
+    active.clear();
+    for (int32_t k = 0; k < n; ++k)
+      if (nsteps[k] > step) active.push_back(sims[k]);
+    for (size_t c0 = 0; c0 < active.size(); c0 += kMaxBatch) {
+      BatchArgs a;
+      a.n = 0;
+      int blocks = 0;
+      const size_t c1 = std::min(active.size(), c0 + size_t(kMaxBatch));
+      for (size_t k = c0; k < c1; ++k) {
+        a.d[a.n++] = desc_of(active[k], blocks);
+        blocks += active[k]->L.nblocks;
+      }
+      hipError_t e = s0->launch(a, blocks, s0->stream);
+      if (e != hipSuccess) return hip_fail(e, "batched step kernel launch");
+      for (size_t k = c0; k < c1; ++k) after_step(active[k]);
+    }
+  }
+  return ELBM_OK;
+}
+
+elbm_status elbm_moments(elbm_sim* s, double* rho, double* u) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (!rho || !u) return fail(ELBM_EINVAL, "rho / u is NULL");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  hipError_t e = launch_moments(box_of(s), s->buf[s->cur], rho, u, s->stream);
+  return e == hipSuccess ? ELBM_OK : hip_fail(e, "elbm_moments");
+}
+
+elbm_status elbm_populations(elbm_sim* s, double* f) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (!f) return fail(ELBM_EINVAL, "f is NULL");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  hipError_t e = launch_gather(box_of(s), s->buf[s->cur], nullptr, s->L.N, 0, f, s->stream);
+  return e == hipSuccess ? ELBM_OK : hip_fail(e, "elbm_populations");
+}
+
+elbm_status elbm_gather(elbm_sim* s, const int64_t* sites, int64_t n, int32_t which,
+                        double* out) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (n < 0 || (n > 0 && (!sites || !out))) return fail(ELBM_EINVAL, "bad gather arguments");
+  if (which != 0 && which != 1) return fail(ELBM_EINVAL, "which must be 0 or 1");
+  if (which == 1 && s->t == 0) return fail(ELBM_ESTATE, "no step has been taken yet");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  hipError_t e = launch_gather(box_of(s), s->buf[s->cur], sites, n, which, out, s->stream);
+  return e == hipSuccess ? ELBM_OK : hip_fail(e, "elbm_gather");
+}
+
+elbm_status elbm_alpha_field(elbm_sim* s, double* alpha) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (!alpha) return fail(ELBM_EINVAL, "alpha is NULL");
+  if (!(s->cfg.diag & ELBM_DIAG_ALPHA)) return fail(ELBM_ESTATE, "ELBM_DIAG_ALPHA is off");
+  if (!s->have_alpha) return fail(ELBM_ESTATE, "no step has recorded alpha yet");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  hipError_t e = launch_copy_f64(s->alpha, alpha, s->L.N, s->stream);
+  return e == hipSuccess ? ELBM_OK : hip_fail(e, "elbm_alpha_field");
+}
+
+elbm_status elbm_stats(elbm_sim* s, elbm_stats_t* out) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (!out) return fail(ELBM_EINVAL, "stats is NULL");
+  if (!(s->cfg.diag & ELBM_DIAG_COUNTS)) return fail(ELBM_ESTATE, "ELBM_DIAG_COUNTS is off");
+  if (!s->have_stats) return fail(ELBM_ESTATE, "no step has recorded diagnostics yet");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  Reduced r;
+  hipError_t e;
+  if ((e = launch_reduce(s->partials, s->L.nblocks, s->reduced, s->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(&r, s->reduced, sizeof r, hipMemcpyDeviceToHost, s->stream)) !=
+          hipSuccess ||
+      (e = hipStreamSynchronize(s->stream)) != hipSuccess)
+    return hip_fail(e, "elbm_stats");
+  out->step = s->t;
+  out->n_sites = s->L.N;
+  out->n_accept2 = r.cnt[0];
+  out->n_alphastar_lt2 = r.cnt[1];
+  out->n_alpha_lt2 = r.cnt[2];
+  out->n_guard = r.cnt[3];
+  out->n_fallback = r.cnt[4];
+  out->n_negative = r.cnt[5];
+  out->n_nonfinite = r.cnt[6];
+  out->total_iters = r.cnt[7];
+  out->alpha_min = r.amin;
+  out->alpha_max = r.amax;
+  out->sum_rho = r.rho;
+  out->sum_j[0] = r.j[0];
+  out->sum_j[1] = r.j[1];
+  out->sum_j[2] = r.j[2];
+  out->sum_H = (s->cfg.diag & ELBM_DIAG_ENTROPY) ? r.H : 0.0;
+  return ELBM_OK;
+}
+
+int64_t elbm_time(const elbm_sim* s) { return s ? s->t : -1; }
+
+elbm_status elbm_destroy(elbm_sim* s) {
+  if (!s) return ELBM_OK;
+  elbm_status st = ELBM_OK;
+  {
+    DeviceGuard g(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) st = hip_fail(e, "elbm_destroy");
+  }
+  delete s;
+  return st;
+}
+
+const char* elbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,260 @@
+// elbm_aux.hip -- auxiliary kernels of the ELBM library: validation and
+// placement of initial states, gathers of f(x,t), moments, and the
+// fixed-order reduction of the per-workgroup diagnostics records.
+//
+// Pull convention: the buffer read by the next step holds P_i(y) with
+// P_i(x - c_i) = f_i(x, t), i.e. the post-collision values of the previous
+// step before streaming (Eq. (5b) is carried out by the reader).
+#include "elbm_internal.hpp"
+#include "elbm_site.hpp"
+
+namespace elbm {
+
+namespace {
+
+struct Coord {
+  int64_t x, y, z;
+};
+
+__device__ __forceinline__ Coord coord_of(const BoxDesc& b, int64_t s) {
+  Coord c;
+  c.x = s % b.nx;
+  const int64_t r = s / b.nx;
+  c.y = r % b.ny;
+  c.z = r / b.ny;
+  return c;
+}
+
+__device__ __forceinline__ int64_t wrapi(int64_t v, int64_t n) {
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// site index of x - c_i
+template <int D>
+__device__ __forceinline__ int64_t upstream(const BoxDesc& b, const Coord& c, int i) {
+  using L = Lattice<D>;
+  const int64_t x = wrapi(c.x - L::c(i, 0), b.nx);
+  const int64_t y = wrapi(c.y - L::c(i, 1), b.ny);
+  const int64_t z = wrapi(c.z - L::c(i, 2), b.nz);
+  return x + b.nx * (y + b.ny * z);
+}
+
+__global__ void k_validate(int64_t N, int D, const double* __restrict__ rho0,
+                           const double* __restrict__ u0, unsigned long long* bad) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int ok = 1;
+  if (s < N) {
+    ok = rho0[s] > 0.0 && isfinite(rho0[s]);
+    for (int a = 0; a < D; ++a) ok = ok && fabs(u0[a * N + s]) < 1.0;
+  }
+  const unsigned long long nb = __ballot(!ok);
+  if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, (unsigned long long)__popcll(nb));
+}
+
+template <int D, class S>
+__global__ void k_scatter(const BoxDesc b, typename S::T* __restrict__ buf,
+                          const double* __restrict__ rho0, const double* __restrict__ u0,
+                          const double* __restrict__ f, int which) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= b.N) return;
+  const Coord c = coord_of(b, s);
+  double fv[Q];
+  if (which == 0) {
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < D; ++a) u[a] = u0[a * b.N + s];
+    Equilibrium<double, D> eq;
+    eq.build(u);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      fv[i] = rho0[s] * (eq.e[0][L::dg(i, 0)] * eq.e[1][L::dg(i, 1)]) * eq.e[2][L::dg(i, 2)];
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fv[i] = f[i * b.N + s];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    buf[i * b.pitch + upstream<D>(b, c, i)] =
+        Codec<S, double>::enc(fv[i], L::invW(i), b.rho_ref);
+}
+
+template <int D, class S>
+__global__ void k_gather(const BoxDesc b, const typename S::T* __restrict__ buf,
+                         const int64_t* __restrict__ sites, int64_t n, int which,
+                         double* __restrict__ out) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t s = sites ? sites[k] : k;
+  if (s < 0 || s >= b.N) {
+    for (int i = 0; i < Q; ++i) out[i * n + k] = NAN;
+    return;
+  }
+  const Coord c = coord_of(b, s);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t src = which == 0 ? upstream<D>(b, c, i) : s;
+    out[i * n + k] = Codec<S, double>::dec(buf[i * b.pitch + src], L::W(i), b.rho_ref);
+  }
+}
+
+template <int D, class S>
+__global__ void k_moments(const BoxDesc b, const typename S::T* __restrict__ buf,
+                          double* __restrict__ rho, double* __restrict__ u) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= b.N) return;
+  const Coord c = coord_of(b, s);
+  double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double g = Codec<S, double>::dec(buf[i * b.pitch + upstream<D>(b, c, i)], L::W(i), b.rho_ref);
+    r += g;
+    for (int a = 0; a < D; ++a) j[a] += L::c(i, a) * g;
+  }
+  rho[s] = r;
+  for (int a = 0; a < D; ++a) u[a * b.N + s] = j[a] / r;
+}
+
+__global__ void k_reduce(const Partial* __restrict__ p, int n, Reduced* __restrict__ out) {
+  __shared__ double sd[kBlock][7];
+  __shared__ long long sc[kBlock][8];
+  const int t = threadIdx.x;
+  double v[7] = {INFINITY, -INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0};
+  long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = t; k < n; k += kBlock) {
+    const Partial& q = p[k];
+    for (int m = 0; m < 8; ++m) c[m] += q.cnt[m];
+    v[0] = fmin(v[0], q.amin);
+    v[1] = fmax(v[1], q.amax);
+    v[2] += q.rho; v[3] += q.jx; v[4] += q.jy; v[5] += q.jz; v[6] += q.H;
+  }
+  for (int m = 0; m < 7; ++m) sd[t][m] = v[m];
+  for (int m = 0; m < 8; ++m) sc[t][m] = c[m];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      sd[t][0] = fmin(sd[t][0], sd[t + w][0]);
+      sd[t][1] = fmax(sd[t][1], sd[t + w][1]);
+      for (int m = 2; m < 7; ++m) sd[t][m] += sd[t + w][m];
+      for (int m = 0; m < 8; ++m) sc[t][m] += sc[t + w][m];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int m = 0; m < 8; ++m) out->cnt[m] = sc[0][m];
+    out->amin = sd[0][0];
+    out->amax = sd[0][1];
+    out->rho = sd[0][2];
+    out->j[0] = sd[0][3]; out->j[1] = sd[0][4]; out->j[2] = sd[0][5];
+    out->H = sd[0][6];
+  }
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) b[s] = a[s];
+}
+
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <template <int, class> class Fn, class... A>
+hipError_t dispatch(int D, int storage, A&&... a) {
+#define ELBM_ST(DD)                                                            \
+  switch (storage) {                                                           \
+    case kStoreF64: return Fn<DD, StoreF64>::run(a...);                        \
+    case kStoreF32: return Fn<DD, StoreF32>::run(a...);                        \
+    case kStoreF32Dev: return Fn<DD, StoreF32Dev>::run(a...);                  \
+    case kStoreF16Dev: return Fn<DD, StoreF16Dev>::run(a...);                  \
+    default: return hipErrorInvalidValue;                                      \
+  }
+  switch (D) {
+    case 1: ELBM_ST(1)
+    case 2: ELBM_ST(2)
+    case 3: ELBM_ST(3)
+    default: return hipErrorInvalidValue;
+  }
+#undef ELBM_ST
+}
+
+template <int D, class S>
+struct ScatterFn {
+  static hipError_t run(const BoxDesc& b, void* buf, const double* rho0, const double* u0,
+                        const double* f, int which, hipStream_t st) {
+    if (b.N == 0) return hipSuccess;
+    k_scatter<D, S><<<grid_for(b.N, 256), 256, 0, st>>>(b, static_cast<typename S::T*>(buf),
+                                                       rho0, u0, f, which);
+    return hipGetLastError();
+  }
+};
+
+template <int D, class S>
+struct GatherFn {
+  static hipError_t run(const BoxDesc& b, const void* buf, const int64_t* sites, int64_t n,
+                        int which, double* out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    k_gather<D, S><<<grid_for(n, 256), 256, 0, st>>>(b, static_cast<const typename S::T*>(buf),
+                                                    sites, n, which, out);
+    return hipGetLastError();
+  }
+};
+
+template <int D, class S>
+struct MomentsFn {
+  static hipError_t run(const BoxDesc& b, const void* buf, double* rho, double* u,
+                        hipStream_t st) {
+    if (b.N == 0) return hipSuccess;
+    k_moments<D, S><<<grid_for(b.N, 256), 256, 0, st>>>(b, static_cast<const typename S::T*>(buf),
+                                                       rho, u);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t launch_validate_init(const BoxDesc& b, const double* rho0, const double* u0,
+                                unsigned long long* bad, hipStream_t st) {
+  if (b.N == 0) return hipSuccess;
+  k_validate<<<grid_for(b.N, 256), 256, 0, st>>>(b.N, b.D, rho0, u0, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const BoxDesc& b, void* buf, const double* rho0, const double* u0,
+                          const double* f, int which, hipStream_t st) {
+  return dispatch<ScatterFn>(b.D, b.storage, b, buf, rho0, u0, f, which, st);
+}
+
+hipError_t launch_gather(const BoxDesc& b, const void* buf, const int64_t* sites, int64_t n,
+                         int which, double* out, hipStream_t st) {
+  return dispatch<GatherFn>(b.D, b.storage, b, buf, sites, n, which, out, st);
+}
+
+hipError_t launch_moments(const BoxDesc& b, const void* buf, double* rho, double* u,
+                          hipStream_t st) {
+  return dispatch<MomentsFn>(b.D, b.storage, b, buf, rho, u, st);
+}
+
+hipError_t launch_reduce(const void* partials, int nblocks, Reduced* out, hipStream_t st) {
+  k_reduce<<<1, kBlock, 0, st>>>(static_cast<const Partial*>(partials), nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_copy_f64<<<grid_for(n, 256), 256, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+StepLauncher step_launcher(int D, int storage, int mode, int fp64) {
+  switch (D) {
+    case 1: return step_launcher_d1(storage, mode, fp64);
+    case 2: return step_launcher_d2(storage, mode, fp64);
+    case 3: return step_launcher_d3(storage, mode, fp64);
+    default: return nullptr;
+  }
+}
+
+}  // namespace elbm

@@ -1,0 +1,89 @@
+// elbm_internal.hpp -- types shared by the kernels and the host runtime of
+// the ELBM library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace elbm {
+
+constexpr int kBlock = 256;        // threads per workgroup of the step kernel
+constexpr int kMaxBatch = 16;      // simulations per batched launch
+constexpr int kPartialBytes = 128; // one diagnostics record per workgroup
+
+// Diagnostics bits (same values as ELBM_DIAG_* of the public header).
+constexpr int kDiagAlpha = 1, kDiagCounts = 2, kDiagEntropy = 4;
+
+// Storage codes (same values as ELBM_STORE_*).
+constexpr int kStoreF64 = 0, kStoreF32 = 1, kStoreF32Dev = 2, kStoreF16Dev = 3;
+
+// Alpha modes (same values as ELBM_ALPHA_*).
+constexpr int kClosed = 0, kNewton = 1, kBisect = 2, kBGK = 3, kSecant = 4;
+
+// One simulation as the step kernel sees it.  Populations are SoA planes of
+// `pitch` elements: element (i, s) of a buffer is at buf[i * pitch + s].
+// The step kernel reads `src` (post-collision values of the previous step;
+// pulling src_i(x - c_i) gives f_i(x, t)) and writes `dst` at each site.
+struct SimDesc {
+  const void* src;
+  void* dst;
+  double* alpha;    // alpha(x) of this step, or nullptr
+  void* partials;   // nblocks diagnostics records, or nullptr
+  int64_t pitch;
+  double beta, rho_ref, root_tol;
+  int32_t nx, ny, nz, rows;  // rows = ny * nz x-rows of nx sites
+  int32_t nblocks;           // workgroups given to this simulation
+  int32_t block_begin;       // first workgroup of this simulation
+  int32_t root_max_iter, secant_iters;
+  int32_t diag;              // kDiag* bits for this step
+  int32_t pad_;
+};
+
+struct BatchArgs {
+  SimDesc d[kMaxBatch];
+  int32_t n;
+};
+
+// Per-workgroup diagnostics record (kPartialBytes bytes).
+struct Partial {
+  int64_t cnt[8];  // accept2, astar_lt2, alpha_lt2, guard, fallback, negative, nonfinite, iters
+  double amin, amax, rho, jx, jy, jz, H, pad;
+};
+static_assert(sizeof(Partial) == kPartialBytes, "partial record size");
+
+// Reduced diagnostics (layout of elbm_stats_t after its `step` field).
+struct Reduced {
+  int64_t n_sites;
+  int64_t cnt[8];
+  double amin, amax, rho, j[3], H;
+};
+
+// Launchers (defined in the kernel translation units).  Each returns the
+// hipError_t of its launch.
+using StepLauncher = hipError_t (*)(const BatchArgs&, int grid, hipStream_t);
+StepLauncher step_launcher(int D, int storage, int mode, int fp64);
+StepLauncher step_launcher_d1(int storage, int mode, int fp64);
+StepLauncher step_launcher_d2(int storage, int mode, int fp64);
+StepLauncher step_launcher_d3(int storage, int mode, int fp64);
+
+// Auxiliary kernels: layout of `state` as in SimDesc (pitch, buffer `buf`).
+struct BoxDesc {
+  int D, storage;
+  int32_t nx, ny, nz;
+  int64_t N, pitch;
+  double rho_ref;
+};
+hipError_t launch_validate_init(const BoxDesc& b, const double* rho0, const double* u0,
+                                unsigned long long* bad, hipStream_t st);
+// which = 0: write f^eq(rho0, u0) in pull convention; 1: write given f(x,t)
+hipError_t launch_scatter(const BoxDesc& b, void* buf, const double* rho0, const double* u0,
+                          const double* f, int which, hipStream_t st);
+// which = 0: pre-collision f(x,t) (pull); 1: stored value at x
+hipError_t launch_gather(const BoxDesc& b, const void* buf, const int64_t* sites, int64_t n,
+                         int which, double* out, hipStream_t st);
+hipError_t launch_moments(const BoxDesc& b, const void* buf, double* rho, double* u,
+                          hipStream_t st);
+hipError_t launch_reduce(const void* partials, int nblocks, Reduced* out, hipStream_t st);
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);
+
+}  // namespace elbm

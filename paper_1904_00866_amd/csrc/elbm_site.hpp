@@ -1,0 +1,187 @@
+// elbm_site.hpp -- per-site arithmetic of the entropic lattice Boltzmann step
+// for gfx950: lattice constants, population storage codecs, the entropic
+// equilibrium, the relaxation parameter alpha and the collision.
+//
+// Method: Zhao & Yong, "Relaxation-rate formula for the entropic lattice
+// Boltzmann method".  Per site:
+//   rho, rho u                      conservation constraints after Eq. (3)
+//   f^eq = argmin H, H = sum f ln(f/W)   Eq. (3) and the constraints
+//   alpha_max, alpha_*              definition after Eq. (7), Eq. (8)
+//   alpha = alpha_* if H(f*(alpha_*)) <= H(f), else Eq. (9)
+//   f~ = f + alpha beta (f^eq - f)  Eq. (1) / Eq. (5a)
+// Comparators: Eq. (4) by bracketed Newton or by bisection (the stop window of
+// the double-shear comparison), the modified secant iteration of the closing
+// remark, and LBGK (alpha = 2, polynomial equilibrium; named after Eq. (4)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace elbm {
+
+// ---------------------------------------------------------------- lattice --
+// Directions are the tensor product of {0, +1, -1} per axis:
+//   i = d(c_x) + 3 d(c_y) + 9 d(c_z),  d(0) = 0, d(+1) = 1, d(-1) = 2.
+// The weights factorise, W_i = prod_a w(c_ia), w(0) = 2/3, w(+-1) = 1/6,
+// and c_s^2 = 1/3 (lattice units).
+__host__ __device__ constexpr int ipow3(int d) { return d == 0 ? 1 : 3 * ipow3(d - 1); }
+__host__ __device__ constexpr int digit(int i, int a) {
+  return (a == 0 ? i : a == 1 ? i / 3 : i / 9) % 3;
+}
+__host__ __device__ constexpr int cval(int dg) { return dg == 0 ? 0 : (dg == 1 ? 1 : -1); }
+
+template <int D>
+struct Lattice {
+  static constexpr int Q = ipow3(D);
+  __host__ __device__ static constexpr int c(int i, int a) { return a < D ? cval(digit(i, a)) : 0; }
+  __host__ __device__ static constexpr int dg(int i, int a) { return a < D ? digit(i, a) : 0; }
+  // W_i = 4^(number of zero components) / 6^D; exact as a quotient of
+  // small integers and its reciprocal 6^D / 4^k is exact in binary.
+  __host__ __device__ static constexpr int nzero(int i) {
+    return (D > 0 && digit(i, 0) == 0) + (D > 1 && digit(i, 1) == 0) + (D > 2 && digit(i, 2) == 0);
+  }
+  __host__ __device__ static constexpr double den() { return D == 1 ? 6.0 : D == 2 ? 36.0 : 216.0; }
+  __host__ __device__ static constexpr double num(int i) {
+    return nzero(i) == 0 ? 1.0 : nzero(i) == 1 ? 4.0 : nzero(i) == 2 ? 16.0 : 64.0;
+  }
+  __host__ __device__ static constexpr double W(int i) { return num(i) / den(); }
+  __host__ __device__ static constexpr double invW(int i) { return den() / num(i); }
+};
+
+// ---------------------------------------------------------------- storage --
+// Populations live in SoA planes of one of four element types.  The
+// deviation formats hold s_i = f_i / W_i - rho_ref, so that the stored
+// number is O(|u| + |x|) whatever the weight; decode f_i = W_i (rho_ref + s_i).
+struct StoreF64 {
+  using T = double;
+  static constexpr bool dev = false;
+};
+struct StoreF32 {
+  using T = float;
+  static constexpr bool dev = false;
+};
+struct StoreF32Dev {
+  using T = float;
+  static constexpr bool dev = true;
+};
+struct StoreF16Dev {
+  using T = _Float16;
+  static constexpr bool dev = true;
+};
+
+template <class S, class R>
+struct Codec {
+  __device__ static __forceinline__ R dec(typename S::T v, R W, R rho_ref) {
+    if constexpr (S::dev) return W * (rho_ref + (R)v);
+    else return (R)v;
+  }
+  __device__ static __forceinline__ typename S::T enc(R f, R invW, R rho_ref) {
+    if constexpr (S::dev) return (typename S::T)(f * invW - rho_ref);
+    else return (typename S::T)f;
+  }
+};
+
+// -------------------------------------------------------------- precision --
+template <class R>
+struct Prec;
+template <>
+struct Prec<double> {
+  // Series lengths K1 < K2 < K3 and the largest max_i |x_i| (thr1..thr3) for
+  // which each leaves an alpha error below 2^-53: truncating E and O after K
+  // terms changes alpha by about 2 x^(2K+1) / ((2K+3)(2K+2)).
+  static constexpr int K1 = 4, K2 = 8, K3 = 14;
+  static constexpr double thr1 = 0.025, thr2 = 0.15, thr3 = 0.30;
+  static constexpr double guard = 1e-26;
+  __device__ static __forceinline__ double log1p_(double y) { return ::log1p(y); }
+  __device__ static __forceinline__ double sqrt_(double y) { return ::sqrt(y); }
+};
+template <>
+struct Prec<float> {
+  // Same bound at 2^-24.
+  static constexpr int K1 = 2, K2 = 4, K3 = 7;
+  static constexpr float thr1 = 0.06f, thr2 = 0.24f, thr3 = 0.30f;
+  static constexpr float guard = 1e-30f;
+  __device__ static __forceinline__ float log1p_(float y) { return ::log1pf(y); }
+  __device__ static __forceinline__ float sqrt_(float y) { return ::sqrtf(y); }
+};
+
+// ------------------------------------------------------------ equilibrium --
+// The minimiser of H under mass and momentum is f_i^eq = W_i exp(l0 + l.c_i).
+// With tensor-product weights it factorises per axis a:
+//   s_a = sqrt(1 + 3 u_a^2), A_a = 2 - s_a, z_a = (2 u_a + s_a) / (1 - u_a),
+//   f_i^eq = rho prod_a w(c_ia) A_a z_a^(c_ia),        |u_a| < 1.
+// e[a][d] holds w(c) A_a z_a^c for digit d of c, ie[a][d] its reciprocal, so
+// f^eq and 1/f^eq cost one product chain per direction and one division per
+// axis.
+template <class R, int D>
+struct Equilibrium {
+  R e[3][3];
+  R ie[3][3];
+  R lnA[3], lnz[3];  // only filled by the entropy diagnostic
+
+  __device__ __forceinline__ void build(const R u[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < D) {
+        const R ua = u[a];
+        const R s = Prec<R>::sqrt_(R(1) + R(3) * ua * ua);
+        const R A = R(2) - s;
+        const R nu = R(2) * ua + s;  // z = nu / de
+        const R de = R(1) - ua;
+        const R r = R(1) / (nu * de * A);
+        const R zp = nu * nu * A * r;  // z
+        const R zm = de * de * A * r;  // 1/z
+        const R iA = nu * de * r;      // 1/A
+        e[a][0] = A * R(2.0 / 3.0);
+        e[a][1] = A * zp * R(1.0 / 6.0);
+        e[a][2] = A * zm * R(1.0 / 6.0);
+        ie[a][0] = iA * R(1.5);
+        ie[a][1] = iA * zm * R(6);
+        ie[a][2] = iA * zp * R(6);
+      } else {
+        e[a][0] = e[a][1] = e[a][2] = R(1);
+        ie[a][0] = ie[a][1] = ie[a][2] = R(1);
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------- entropy sums --
+// phi(y) = (1+y) ln(1+y) - y.  Because ln(f^eq_i/W_i) is affine in (1, c_i),
+// any g with the moments of f^eq has H(g) - H(f^eq) = sum_i f^eq_i phi(g_i/f^eq_i - 1).
+// With x_i = f_i/f^eq_i - 1 and f*(alpha) = f^eq (1 + (1 - alpha) x):
+//   D      = H(f) - H(f^eq)          = sum f^eq phi(x)
+//   G(a)   = H(f*(a)) - H(f)         = sum f^eq [phi((1-a)x) - phi(x)]
+//   D*(a)  = H(f*(a)) - H(f^eq)      = sum f^eq phi((1-a)x)   (Eq. (9) denominator)
+// At alpha_* = 2 the Maclaurin series of ln(1 +- x) give, with
+//   E(x) = sum_k x^(2k) / (2k (2k-1)),  O(x) = sum_k x^(2k+1) / ((2k+1) 2k),
+//   phi(x) = E - O, phi(-x) = E + O, G(2) = 2 sum f^eq O: no cancellation.
+template <class R>
+__device__ __forceinline__ R phi_log(R y) {
+  // y <= -1 only arises as the rounding of (1 - alpha_max) x_k = -1, i.e. a
+  // population driven exactly to zero: the 0 ln 0 = 0 limit is phi = 1.
+  if (y <= R(-1)) return R(1);
+  return (R(1) + y) * Prec<R>::log1p_(y) - y;
+}
+
+template <class R>
+__device__ __forceinline__ R dlog_clamped(R y) {
+  return Prec<R>::log1p_(y < R(-1) ? R(-1) : y);
+}
+
+// Horner in t = x^2 for E(x)/t and O(x)/(x t), K terms each.
+template <class R, int K>
+__device__ __forceinline__ void series_EO(R x, R& E, R& O) {
+  const R t = x * x;
+  R pe = R(1.0 / ((2.0 * K) * (2.0 * K - 1.0)));
+  R po = R(1.0 / ((2.0 * K + 1.0) * (2.0 * K)));
+#pragma unroll
+  for (int k = K - 1; k >= 1; --k) {
+    pe = pe * t + R(1.0 / ((2.0 * k) * (2.0 * k - 1.0)));
+    po = po * t + R(1.0 / ((2.0 * k + 1.0) * (2.0 * k)));
+  }
+  E = pe * t;
+  O = po * t * x;
+}
+
+}  // namespace elbm

@@ -1,0 +1,9 @@
+// elbm_step_d3.hip -- step-kernel instantiations for the D3Q27 lattice
+// (one translation unit per lattice so that they compile in parallel).
+#include "elbm_step_impl.hpp"
+
+namespace elbm {
+StepLauncher step_launcher_d3(int storage, int mode, int fp64) {
+  return step_launcher_for<3>(storage, mode, fp64);
+}
+}  // namespace elbm

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/elbm.h declares, its structs have the header's
+layout, and configuration errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1904_00866_amd import elbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "elbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(elbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = elbm.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(elbm.EXPORTS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(f'''#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+int main(void) {{
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(elbm_config), offsetof(elbm_config, beta),
+         offsetof(elbm_config, rho_ref), offsetof(elbm_config, diag), sizeof(elbm_stats_t));
+  return 0;
+}}''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    want = [C.sizeof(elbm.Config), elbm.Config.beta.offset, elbm.Config.rho_ref.offset,
+            elbm.Config.diag.offset, C.sizeof(elbm.Stats)]
+    assert [int(v) for v in got] == want
+
+
+def test_default_config_and_state_bytes():
+    cfg = elbm.make_config("d3q27", 64, 64, 64)
+    assert cfg.alpha_mode == 0 and cfg.storage == 1 and cfg.alpha_fp64 == 1
+    assert abs(cfg.beta - 0.95) < 1e-15 and cfg.root_tol == 1e-13
+    nb = elbm.state_bytes(cfg)
+    assert nb >= 2 * 27 * 64 ** 3 * 4
+    assert nb < 2 * 27 * (64 ** 3 + 1024) * 4 + 65536
+    cfg16 = elbm.make_config("d3q27", 64, 64, 64, storage="f16dev")
+    assert elbm.state_bytes(cfg16) < nb
+    cfgd = elbm.make_config("d3q27", 64, 64, 64, diag=elbm.DIAG_ALPHA | elbm.DIAG_COUNTS)
+    assert elbm.state_bytes(cfgd) >= nb + 8 * 64 ** 3
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(beta=1.0), "beta"),
+    (dict(beta=0.0), "beta"),
+    (dict(mode="newton", fp64=False), "FP32 arithmetic"),
+    (dict(storage="f64", fp64=False), "FP64 storage"),
+    (dict(diag=elbm.DIAG_ENTROPY), "ENTROPY"),
+    (dict(diag=64), "diagnostics"),
+    (dict(storage="f16dev", rho_ref=0.0), "rho_ref"),
+    (dict(mode="secant", secant_iters=0), "secant"),
+])
+def test_invalid_configs_are_rejected(kw, msg):
+    cfg = elbm.make_config("d2q9", 32, 32, 1, **kw)
+    assert elbm.lib().elbm_state_bytes(C.byref(cfg)) == 0
+    assert msg in elbm.lib().elbm_last_error().decode()
+
+
+@pytest.mark.parametrize("dims,msg", [
+    (("d2q9", 32, 32, 2), "nz = 1"),
+    (("d1q3", 32, 2, 1), "ny = nz = 1"),
+    (("d3q27", 0, 4, 4), ">= 1"),
+    (("d3q27", 2 ** 20, 4, 4), "extent"),
+    (("d3q27", 2048, 2048, 1024), "sites exceed"),
+    (("d3q27", 1024, 1024, 1100), "4 GiB"),
+])
+def test_invalid_boxes_are_rejected(dims, msg):
+    cfg = elbm.make_config(*dims)
+    assert elbm.lib().elbm_state_bytes(C.byref(cfg)) == 0
+    assert msg in elbm.lib().elbm_last_error().decode()
+
+
+def test_init_argument_errors_before_device_work():
+    L = elbm.lib()
+    cfg = elbm.make_config("d2q9", 8, 8, 1)
+    h = C.c_void_p()
+    assert L.elbm_init(C.byref(cfg), None, None, None, 0, None, C.byref(h)) == -1
+    assert b"dev_state" in L.elbm_last_error()
+    assert L.elbm_init(C.byref(cfg), None, None, C.c_void_p(256), 10, None, C.byref(h)) == -3
+    assert L.elbm_init(C.byref(cfg), None, None, C.c_void_p(255), 1 << 30, None,
+                       C.byref(h)) == -1
+    assert b"aligned" in L.elbm_last_error()
+    assert L.elbm_init(C.byref(cfg), None, None, C.c_void_p(256), 1 << 30, None, None) == -1
+    assert L.elbm_step(None, 1) == -1
+    assert L.elbm_destroy(None) == 0
+    assert L.elbm_time(None) == -1
+
+
+def test_batch_argument_errors():
+    L = elbm.lib()
+    assert L.elbm_step_batch(None, None, 0) == 0
+    assert L.elbm_step_batch(None, None, -1) == -1
+    assert L.elbm_step_batch(None, None, 2) == -1
