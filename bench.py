@@ -123,6 +123,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None, choices=["closed", "newton", "bisect", "bgk"],
                     help="time one alpha mode only (profiling runs)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (a known-size kernel "
+                         "that calibrates hardware byte counters in profiling runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -141,6 +144,14 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     elbm.lib()
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del a, b
+        torch.cuda.empty_cache()
     n, storage = args.n, args.storage
     N = n ** 3
     beta = Wk.tgv3d_beta(n)

@@ -95,8 +95,9 @@ enum {
 /* Diagnostics switches (bit mask). */
 enum {
   ELBM_DIAG_ALPHA = 1u,  /* record alpha(x) of every step (8 B/site extra) */
-  ELBM_DIAG_COUNTS = 2u, /* per-step counts, alpha range, mass, momentum  */
-  ELBM_DIAG_ENTROPY = 4u /* also sum_x H(f(x,t)) (Eq. (6)); needs COUNTS  */
+  ELBM_DIAG_COUNTS = 2u, /* per-step site counts and the alpha range      */
+  ELBM_DIAG_SUMS = 4u    /* also sum_x rho, rho u and H(f(x,t)) (Eq. (6)); */
+                         /* needs COUNTS                                  */
 };
 
 typedef struct {
@@ -129,13 +130,13 @@ typedef struct {
   int64_t n_alpha_lt2;     /* sites with alpha < 2                         */
   int64_t n_guard;         /* sites with f = f^eq to rounding              */
   int64_t n_fallback;      /* sites evaluated with log1p, not the series   */
-  int64_t n_negative;      /* post-collision populations < 0               */
-  int64_t n_nonfinite;     /* post-collision populations NaN or inf        */
+  int64_t n_negative;      /* sites with a post-collision population < 0   */
+  int64_t n_nonfinite;     /* sites whose rho, u or alpha is NaN or inf    */
   int64_t total_iters;     /* root-solver / secant iterations, summed      */
-  double alpha_min, alpha_max;
-  double sum_rho;          /* sum_x rho(x,t)                               */
-  double sum_j[3];         /* sum_x rho u(x,t)                             */
-  double sum_H;            /* sum_x H(f(x,t)) if ELBM_DIAG_ENTROPY, else 0 */
+  double alpha_min, alpha_max; /* range of alpha (float precision)        */
+  double sum_rho;          /* sum_x rho(x,t)        (ELBM_DIAG_SUMS, else 0) */
+  double sum_j[3];         /* sum_x rho u(x,t)      (ELBM_DIAG_SUMS, else 0) */
+  double sum_H;            /* sum_x H(f(x,t))       (ELBM_DIAG_SUMS, else 0) */
 } elbm_stats_t;
 
 /* Default configuration for a lattice and box (closed-form alpha, FP32

@@ -55,7 +55,7 @@ struct Layout {
   int D, Q, esize;
   int64_t N, pitch;
   int nblocks;
-  size_t off_buf[2], off_alpha, off_partials, off_misc, total;
+  size_t off_buf[2], off_alpha, off_counts, off_sums, off_misc, total;
 };
 
 elbm_status check_config(const elbm_config* c, Layout* L) {
@@ -93,8 +93,8 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   if (c->alpha_mode == ELBM_ALPHA_BISECT && !(c->root_tol >= 0.0))
     return fail(ELBM_EINVAL, "root_tol must be >= 0");
   if (c->diag & ~7u) return fail(ELBM_EINVAL, "unknown diagnostics bits 0x%x", c->diag);
-  if ((c->diag & ELBM_DIAG_ENTROPY) && !(c->diag & ELBM_DIAG_COUNTS))
-    return fail(ELBM_EINVAL, "ELBM_DIAG_ENTROPY needs ELBM_DIAG_COUNTS");
+  if ((c->diag & ELBM_DIAG_SUMS) && !(c->diag & ELBM_DIAG_COUNTS))
+    return fail(ELBM_EINVAL, "ELBM_DIAG_SUMS needs ELBM_DIAG_COUNTS");
   if (c->plane_pad < -1) return fail(ELBM_EINVAL, "plane_pad must be >= -1");
   if (!step_launcher(D, c->storage, c->alpha_mode, c->alpha_fp64))
     return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
@@ -125,8 +125,10 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   off += bufbytes;
   L->off_alpha = off;
   if (c->diag & ELBM_DIAG_ALPHA) off += align_up(size_t(N) * 8, kAlign);
-  L->off_partials = off;
-  if (c->diag & ELBM_DIAG_COUNTS) off += align_up(size_t(L->nblocks) * kPartialBytes, kAlign);
+  L->off_counts = off;
+  if (c->diag & ELBM_DIAG_COUNTS) off += align_up(size_t(L->nblocks) * kCountBytes, kAlign);
+  L->off_sums = off;
+  if (c->diag & ELBM_DIAG_SUMS) off += align_up(size_t(L->nblocks) * kSumBytes, kAlign);
   L->off_misc = off;
   off += align_up(sizeof(Reduced) + 64, kAlign);
   L->total = off;
@@ -159,7 +161,8 @@ struct elbm_sim {
   void* buf[2];
   int cur;  // buffer holding the state that the next step reads
   double* alpha;
-  void* partials;
+  void* counts;
+  void* sums;
   Reduced* reduced;
   unsigned long long* counter;
   hipStream_t stream;
@@ -190,7 +193,8 @@ SimDesc desc_of(const elbm_sim* s, int block_begin) {
   d.src = s->buf[s->cur];
   d.dst = s->buf[1 - s->cur];
   d.alpha = (s->cfg.diag & ELBM_DIAG_ALPHA) ? s->alpha : nullptr;
-  d.partials = (s->cfg.diag & ELBM_DIAG_COUNTS) ? s->partials : nullptr;
+  d.counts = (s->cfg.diag & ELBM_DIAG_COUNTS) ? s->counts : nullptr;
+  d.sums = (s->cfg.diag & ELBM_DIAG_SUMS) ? s->sums : nullptr;
   d.pitch = s->L.pitch;
   d.beta = s->cfg.beta;
   d.rho_ref = s->cfg.rho_ref;
@@ -276,7 +280,8 @@ elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* 
   s->buf[1] = s->base + L.off_buf[1];
   s->cur = 0;
   s->alpha = reinterpret_cast<double*>(s->base + L.off_alpha);
-  s->partials = s->base + L.off_partials;
+  s->counts = s->base + L.off_counts;
+  s->sums = s->base + L.off_sums;
   s->reduced = reinterpret_cast<Reduced*>(s->base + L.off_misc);
   s->counter = reinterpret_cast<unsigned long long*>(s->base + L.off_misc + sizeof(Reduced));
   s->stream = static_cast<hipStream_t>(hip_stream);
@@ -439,7 +444,8 @@ elbm_status elbm_stats(elbm_sim* s, elbm_stats_t* out) {
   if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
   Reduced r;
   hipError_t e;
-  if ((e = launch_reduce(s->partials, s->L.nblocks, s->reduced, s->stream)) != hipSuccess ||
+  const void* sums = (s->cfg.diag & ELBM_DIAG_SUMS) ? s->sums : nullptr;
+  if ((e = launch_reduce(s->counts, sums, s->L.nblocks, s->reduced, s->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(&r, s->reduced, sizeof r, hipMemcpyDeviceToHost, s->stream)) !=
           hipSuccess ||
       (e = hipStreamSynchronize(s->stream)) != hipSuccess)
@@ -460,7 +466,7 @@ elbm_status elbm_stats(elbm_sim* s, elbm_stats_t* out) {
   out->sum_j[0] = r.j[0];
   out->sum_j[1] = r.j[1];
   out->sum_j[2] = r.j[2];
-  out->sum_H = (s->cfg.diag & ELBM_DIAG_ENTROPY) ? r.H : 0.0;
+  out->sum_H = r.H;
   return ELBM_OK;
 }
 

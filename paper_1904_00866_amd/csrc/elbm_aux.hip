@@ -119,38 +119,49 @@ __global__ void k_moments(const BoxDesc b, const typename S::T* __restrict__ buf
   for (int a = 0; a < D; ++a) u[a * b.N + s] = j[a] / r;
 }
 
-__global__ void k_reduce(const Partial* __restrict__ p, int n, Reduced* __restrict__ out) {
-  __shared__ double sd[kBlock][7];
-  __shared__ long long sc[kBlock][8];
+// Fixed-order reduction of the per-workgroup records: thread t folds records
+// t, t + kBlock, ... in order, then a fixed tree combines the threads.
+__global__ void k_reduce(const CountRec* __restrict__ cr, const SumRec* __restrict__ sr, int n,
+                         Reduced* __restrict__ out) {
+  __shared__ double sd[kBlock][5];
+  __shared__ float sa[kBlock][2];
+  __shared__ unsigned long long sc[kBlock][kNumCounts];
   const int t = threadIdx.x;
-  double v[7] = {INFINITY, -INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0};
-  long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  float mn = INFINITY, mx = -INFINITY;
+  unsigned long long c[kNumCounts];
+  for (int m = 0; m < kNumCounts; ++m) c[m] = 0;
   for (int k = t; k < n; k += kBlock) {
-    const Partial& q = p[k];
-    for (int m = 0; m < 8; ++m) c[m] += q.cnt[m];
-    v[0] = fmin(v[0], q.amin);
-    v[1] = fmax(v[1], q.amax);
-    v[2] += q.rho; v[3] += q.jx; v[4] += q.jy; v[5] += q.jz; v[6] += q.H;
+    const CountRec& q = cr[k];
+    for (int m = 0; m < kNumCounts; ++m) c[m] += q.cnt[m];
+    mn = fminf(mn, q.amin);
+    mx = fmaxf(mx, q.amax);
+    if (sr) {
+      const SumRec& w = sr[k];
+      v[0] += w.rho; v[1] += w.j[0]; v[2] += w.j[1]; v[3] += w.j[2]; v[4] += w.H;
+    }
   }
-  for (int m = 0; m < 7; ++m) sd[t][m] = v[m];
-  for (int m = 0; m < 8; ++m) sc[t][m] = c[m];
+  for (int m = 0; m < 5; ++m) sd[t][m] = v[m];
+  sa[t][0] = mn;
+  sa[t][1] = mx;
+  for (int m = 0; m < kNumCounts; ++m) sc[t][m] = c[m];
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if (t < w) {
-      sd[t][0] = fmin(sd[t][0], sd[t + w][0]);
-      sd[t][1] = fmax(sd[t][1], sd[t + w][1]);
-      for (int m = 2; m < 7; ++m) sd[t][m] += sd[t + w][m];
-      for (int m = 0; m < 8; ++m) sc[t][m] += sc[t + w][m];
+      for (int m = 0; m < 5; ++m) sd[t][m] += sd[t + w][m];
+      sa[t][0] = fminf(sa[t][0], sa[t + w][0]);
+      sa[t][1] = fmaxf(sa[t][1], sa[t + w][1]);
+      for (int m = 0; m < kNumCounts; ++m) sc[t][m] += sc[t + w][m];
     }
     __syncthreads();
   }
   if (t == 0) {
-    for (int m = 0; m < 8; ++m) out->cnt[m] = sc[0][m];
-    out->amin = sd[0][0];
-    out->amax = sd[0][1];
-    out->rho = sd[0][2];
-    out->j[0] = sd[0][3]; out->j[1] = sd[0][4]; out->j[2] = sd[0][5];
-    out->H = sd[0][6];
+    for (int m = 0; m < kNumCounts; ++m) out->cnt[m] = (int64_t)sc[0][m];
+    out->amin = sa[0][0];
+    out->amax = sa[0][1];
+    out->rho = sd[0][0];
+    out->j[0] = sd[0][1]; out->j[1] = sd[0][2]; out->j[2] = sd[0][3];
+    out->H = sd[0][4];
   }
 }
 
@@ -237,8 +248,10 @@ hipError_t launch_moments(const BoxDesc& b, const void* buf, double* rho, double
   return dispatch<MomentsFn>(b.D, b.storage, b, buf, rho, u, st);
 }
 
-hipError_t launch_reduce(const void* partials, int nblocks, Reduced* out, hipStream_t st) {
-  k_reduce<<<1, kBlock, 0, st>>>(static_cast<const Partial*>(partials), nblocks, out);
+hipError_t launch_reduce(const void* counts, const void* sums, int nblocks, Reduced* out,
+                         hipStream_t st) {
+  k_reduce<<<1, kBlock, 0, st>>>(static_cast<const CountRec*>(counts),
+                                 static_cast<const SumRec*>(sums), nblocks, out);
   return hipGetLastError();
 }
 

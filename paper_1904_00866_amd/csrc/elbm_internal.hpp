@@ -9,10 +9,11 @@ namespace elbm {
 
 constexpr int kBlock = 256;        // threads per workgroup of the step kernel
 constexpr int kMaxBatch = 16;      // simulations per batched launch
-constexpr int kPartialBytes = 128; // one diagnostics record per workgroup
+constexpr int kCountBytes = 48;    // per-workgroup counts record
+constexpr int kSumBytes = 64;      // per-workgroup sums record
 
 // Diagnostics bits (same values as ELBM_DIAG_* of the public header).
-constexpr int kDiagAlpha = 1, kDiagCounts = 2, kDiagEntropy = 4;
+constexpr int kDiagAlpha = 1, kDiagCounts = 2, kDiagSums = 4;
 
 // Storage codes (same values as ELBM_STORE_*).
 constexpr int kStoreF64 = 0, kStoreF32 = 1, kStoreF32Dev = 2, kStoreF16Dev = 3;
@@ -28,7 +29,8 @@ struct SimDesc {
   const void* src;
   void* dst;
   double* alpha;    // alpha(x) of this step, or nullptr
-  void* partials;   // nblocks diagnostics records, or nullptr
+  void* counts;     // nblocks CountRec records, or nullptr
+  void* sums;       // nblocks SumRec records, or nullptr
   int64_t pitch;
   double beta, rho_ref, root_tol;
   int32_t nx, ny, nz, rows;  // rows = ny * nz x-rows of nx sites
@@ -44,12 +46,21 @@ struct BatchArgs {
   int32_t n;
 };
 
-// Per-workgroup diagnostics record (kPartialBytes bytes).
-struct Partial {
-  int64_t cnt[8];  // accept2, astar_lt2, alpha_lt2, guard, fallback, negative, nonfinite, iters
-  double amin, amax, rho, jx, jy, jz, H, pad;
+// Per-workgroup diagnostics records.  Counts are per site: accepted alpha = 2,
+// alpha_max < 2, alpha < 2, guard, long-series/log1p path, a negative output
+// population, a non-finite rho/u/alpha; then root-solver iterations.
+enum { kCntAccept2 = 0, kCntAstarLt2, kCntAlphaLt2, kCntGuard, kCntFallback, kCntNeg,
+       kCntNonfinite, kCntIters, kNumCounts };
+struct CountRec {
+  uint32_t cnt[kNumCounts];
+  float amin, amax;
+  uint32_t pad[2];
 };
-static_assert(sizeof(Partial) == kPartialBytes, "partial record size");
+static_assert(sizeof(CountRec) == kCountBytes, "count record size");
+struct SumRec {
+  double rho, j[3], H, pad[3];
+};
+static_assert(sizeof(SumRec) == kSumBytes, "sum record size");
 
 // Reduced diagnostics (layout of elbm_stats_t after its `step` field).
 struct Reduced {
@@ -83,7 +94,8 @@ hipError_t launch_gather(const BoxDesc& b, const void* buf, const int64_t* sites
                          int which, double* out, hipStream_t st);
 hipError_t launch_moments(const BoxDesc& b, const void* buf, double* rho, double* u,
                           hipStream_t st);
-hipError_t launch_reduce(const void* partials, int nblocks, Reduced* out, hipStream_t st);
+hipError_t launch_reduce(const void* counts, const void* sums, int nblocks, Reduced* out,
+                         hipStream_t st);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);
 
 }  // namespace elbm

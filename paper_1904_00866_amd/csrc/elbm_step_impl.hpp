@@ -11,18 +11,20 @@
 // so that dst, pulled at the next step, is f(x, t+1).  Every value of src is
 // read exactly once per step, every value of dst written once: 2 Q b bytes
 // per site update for b-byte storage.
+//
+// Register budget.  The populations stay in registers in their storage type;
+// x_i and f^eq_i are recomputed from per-axis factors wherever they are
+// needed instead of being kept (Q doubles each).  The common case -- alpha_* =
+// 2 and max_i |x_i| small -- is one unrolled pass with a short series.  Rare
+// cases (a longer series, the log1p forms, the root solvers) run as
+// non-unrolled loops over the directions so they add little register
+// pressure to the common path.
 #pragma once
 
 #include "elbm_internal.hpp"
 #include "elbm_site.hpp"
 
 namespace elbm {
-
-template <class R>
-struct AlphaOut {
-  R alpha, D;
-  int accepted2, astar_lt2, guard, fallback, iters;
-};
 
 // Keeps a value in registers but hides it from the optimiser, so that
 // quantities derived from it are recomputed where they are used instead of
@@ -33,51 +35,101 @@ __device__ __forceinline__ R opaque(R v) {
   return v;
 }
 
-// One site's loaded populations and its equilibrium factors.  x_i and
-// f^eq_i are recomputed from them in each pass instead of being stored.
-template <int D, class S, class R>
-struct SiteView {
-  using L = Lattice<D>;
-  static constexpr int Q = L::Q;
-  typename S::T raw[Q];
-  R rho, irho, rho_ref;
-  Equilibrium<R, D> eq;
+template <class R>
+__device__ __forceinline__ R sel3(const R (&a)[3], int d) {
+  return d == 0 ? a[0] : (d == 1 ? a[1] : a[2]);
+}
 
-  // The loaded value passes through opaque() so that its conversion is
-  // redone in each pass rather than Q converted values being kept live.
+// Lengths of the common-path series and its validity bound: truncating
+// E and O after K terms changes alpha by about 2 x^(2K+1)/((2K+3)(2K+2)),
+// below 2^-53 (FP64) / 2^-24 (FP32) for max_i |x_i| up to the bound.
+template <class R>
+struct Base;
+template <>
+struct Base<double> {
+  static constexpr int K = 3;
+  static constexpr double thr = 8.5e-3;
+  static constexpr int KL = 14;  // long series of the rare path
+  static constexpr double thrL = 0.30;
+};
+template <>
+struct Base<float> {
+  static constexpr int K = 2;
+  static constexpr float thr = 0.06f;
+  static constexpr int KL = 7;
+  static constexpr float thrL = 0.30f;
+};
+
+// One site's loaded populations, density and equilibrium factors.
+template <int D, class S, class R>
+struct Site {
+  using L = Lattice<D>;
+  using T = typename S::T;
+  static constexpr int Q = L::Q;
+  T raw[Q];
+  R rho, irho, rho_ref;
+  R u[3];
+  R e[3][3];   // e[a][d]  = w(c) A_a z_a^c   (digit d of c)
+  R ie[3][3];  // ie[a][d] = 1 / e[a][d]
+  // where the populations came from, for the loops of the rare paths
+  const T* src;
+  int64_t pitch;
+  uint32_t xs[3], ys[3], zs[3];
+
+  // -- unrolled accessors (compile-time i) --------------------------------
+  // The loaded value passes through opaque() so that its conversion is redone
+  // in each pass rather than Q converted values being kept live.
   __device__ __forceinline__ R g(int i) const {
     return Codec<S, R>::dec(opaque(raw[i]), R(L::W(i)), rho_ref);
   }
-  // f^eq_i = rho prod_a e[a][d_a(i)]
   __device__ __forceinline__ R fe(int i, R r) const {
-    return r * (eq.e[0][L::dg(i, 0)] * eq.e[1][L::dg(i, 1)]) * eq.e[2][L::dg(i, 2)];
+    return r * (e[0][L::dg(i, 0)] * e[1][L::dg(i, 1)]) * e[2][L::dg(i, 2)];
   }
-  // x_i = g_i / f^eq_i - 1, with 1/f^eq_i = (1/rho) prod_a ie[a][d_a(i)]
   __device__ __forceinline__ R x(int i, R ir) const {
-    const R ri = ir * (eq.ie[0][L::dg(i, 0)] * eq.ie[1][L::dg(i, 1)]) * eq.ie[2][L::dg(i, 2)];
+    const R ri = ir * (ie[0][L::dg(i, 0)] * ie[1][L::dg(i, 1)]) * ie[2][L::dg(i, 2)];
     return fma(g(i), ri, R(-1));
+  }
+
+  // -- loop accessors (run-time, wavefront-uniform i) -----------------------
+  // Register arrays are never indexed at run time (that would move them to
+  // scratch memory); the population is re-read from the source buffer,
+  // whose lines this wavefront has just brought into the caches.
+  __device__ __forceinline__ void xfe(int i, R& xi, R& fi) const {
+    const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
+    const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
+    const R W = R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0) / R(L::den());
+    const uint32_t off = sel3(zs, dz) + sel3(ys, dy) + sel3(xs, dx);
+    const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(src + (int64_t)i * pitch) +
+                                            off * (uint32_t)sizeof(T));
+    const R gi = Codec<S, R>::dec(*p, W, rho_ref);
+    fi = rho * (sel3(e[0], dx) * sel3(e[1], dy)) * sel3(e[2], dz);
+    const R ri = irho * (sel3(ie[0], dx) * sel3(ie[1], dy)) * sel3(ie[2], dz);
+    xi = fma(gi, ri, R(-1));
   }
 };
 
 // S(a) = sum_i f^eq_i phi((1 - a) x_i); G(a) = H(f*(a)) - H(f) = S(a) - D.
 template <int D, class S, class R>
-__device__ __forceinline__ R S_log(const SiteView<D, S, R>& v, R a) {
-  const R r = opaque(v.rho), ir = opaque(v.irho);
+__device__ __forceinline__ R S_log(const Site<D, S, R>& v, R a) {
   R s = R(0);
-#pragma unroll
-  for (int i = 0; i < SiteView<D, S, R>::Q; ++i) s += v.fe(i, r) * phi_log<R>((R(1) - a) * v.x(i, ir));
+#pragma unroll 1
+  for (int i = 0; i < Site<D, S, R>::Q; ++i) {
+    R xi, fi;
+    v.xfe(i, xi, fi);
+    s += fi * phi_log<R>((R(1) - a) * xi);
+  }
   return s;
 }
 
 // S(a) and S'(a) = G'(a) = -sum_i f^eq_i x_i ln(1 + (1 - a) x_i).
 template <int D, class S, class R>
-__device__ __forceinline__ void S_dS_log(const SiteView<D, S, R>& v, R a, R& Sv, R& dS) {
-  const R r = opaque(v.rho), ir = opaque(v.irho);
+__device__ __forceinline__ void S_dS_log(const Site<D, S, R>& v, R a, R& Sv, R& dS) {
   Sv = R(0);
   dS = R(0);
-#pragma unroll
-  for (int i = 0; i < SiteView<D, S, R>::Q; ++i) {
-    const R xi = v.x(i, ir), fi = v.fe(i, r);
+#pragma unroll 1
+  for (int i = 0; i < Site<D, S, R>::Q; ++i) {
+    R xi, fi;
+    v.xfe(i, xi, fi);
     const R y = (R(1) - a) * xi;
     const R l = dlog_clamped<R>(y);
     Sv += fi * ((y <= R(-1)) ? R(1) : (R(1) + y) * l - y);
@@ -85,38 +137,69 @@ __device__ __forceinline__ void S_dS_log(const SiteView<D, S, R>& v, R a, R& Sv,
   }
 }
 
-template <int K, int D, class S, class R>
-__device__ __forceinline__ void series_sums(const SiteView<D, S, R>& v, R& sE, R& sO) {
-  const R r = opaque(v.rho), ir = opaque(v.irho);
-  sE = R(0);
-  sO = R(0);
-#pragma unroll
-  for (int i = 0; i < SiteView<D, S, R>::Q; ++i) {
-    R E, O;
-    series_EO<R, K>(v.x(i, ir), E, O);
-    const R fi = v.fe(i, r);
-    sE += fi * E;
-    sO += fi * O;
+// The rare path of one lane: the long series when alpha_* = 2 and
+// max|x| <= thrL, else the log1p forms.
+template <int D, class S, class R>
+__device__ __forceinline__ void rare_sums(const Site<D, S, R>& v, R astar, bool star2, R xabs, R& Dv, R& Ds,
+                          R& Gs) {
+  constexpr int Q = Site<D, S, R>::Q;
+  if (star2 && xabs <= Base<R>::thrL) {
+    R sE = R(0), sO = R(0);
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      R xi, fi, E, O;
+      v.xfe(i, xi, fi);
+      series_EO<R, Base<R>::KL>(xi, E, O);
+      sE += fi * E;
+      sO += fi * O;
+    }
+    Dv = sE - sO;
+    Ds = sE + sO;
+    Gs = R(2) * sO;
+    return;
   }
+  R sD = R(0), sS = R(0), sG = R(0);
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    R xi, fi;
+    v.xfe(i, xi, fi);
+    const R px = phi_log<R>(xi);
+    const R py = phi_log<R>((R(1) - astar) * xi);
+    sD += fi * px;
+    sS += fi * py;
+    sG += fi * (py - px);
+  }
+  Dv = sD;
+  Ds = sS;
+  Gs = sG;
 }
 
-// The choice of alpha at one site.
+template <class R>
+struct AlphaOut {
+  R alpha, D;
+  bool accepted2, astar_lt2, guard, fallback;
+  int iters;
+};
+
+// The choice of alpha at one site (all lanes of the wavefront call it).
 template <int MODE, int D, class S, class R>
-__device__ __forceinline__ AlphaOut<R> choose_alpha(const SiteView<D, S, R>& v, const SimDesc& d) {
-  constexpr int Q = SiteView<D, S, R>::Q;
+__device__ __forceinline__ AlphaOut<R> choose_alpha(const Site<D, S, R>& v, const SimDesc& d) {
+  constexpr int Q = Site<D, S, R>::Q;
   AlphaOut<R> o;
-  o.fallback = 0;
-  R xmax, xabs;
+  // Common pass: x_i, the x range, and the K-term series sums together.
+  R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   {
-    const R ir = v.irho;
-    const R x0 = v.x(0, ir);
-    xmax = x0;
-    xabs = fabs(x0);
+    const R r = opaque(v.rho), ir = opaque(v.irho);
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
+    for (int i = 0; i < Q; ++i) {
       const R xi = v.x(i, ir);
       xmax = fmax(xmax, xi);
       xabs = fmax(xabs, fabs(xi));
+      R E, O;
+      series_EO<R, Base<R>::K>(xi, E, O);
+      const R fi = v.fe(i, r);
+      sE = fma(fi, E, sE);
+      sO = fma(fi, O, sO);
     }
   }
   // alpha_max = min over {f^eq_i < f_i} of f_i/(f_i - f^eq_i) = 1 + 1/max_i x_i
@@ -126,36 +209,13 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(const SiteView<D, S, R>& v, 
   const R amax = has_pos ? R(1) + R(1) / xmax : R(INFINITY);
   const bool star2 = !(xmax > R(1));
   const R astar = star2 ? R(2) : amax;
-
-  // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq)
-  R Dv, Gs, Ds;
-  if (star2 && xabs <= Prec<R>::thr3) {
-    // series branch; its length is uniform across the wavefront
-    const bool need2 = __any(xabs > Prec<R>::thr1);
-    const bool need3 = __any(xabs > Prec<R>::thr2);
-    R sE, sO;
-    if (need3) series_sums<Prec<R>::K3>(v, sE, sO);
-    else if (need2) series_sums<Prec<R>::K2>(v, sE, sO);
-    else series_sums<Prec<R>::K1>(v, sE, sO);
-    Dv = sE - sO;
-    Ds = sE + sO;
-    Gs = R(2) * sO;
-  } else {
-    o.fallback = 1;
-    const R r = opaque(v.rho), ir = opaque(v.irho);
-    R sD = R(0), sS = R(0), sG = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R xi = v.x(i, ir), fi = v.fe(i, r);
-      const R px = phi_log<R>(xi);
-      const R py = phi_log<R>((R(1) - astar) * xi);
-      sD += fi * px;
-      sS += fi * py;
-      sG += fi * (py - px);
-    }
-    Dv = sD;
-    Ds = sS;
-    Gs = sG;
+  // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
+  // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
+  R Dv = sE - sO, Ds = sE + sO, Gs = R(2) * sO;
+  const bool common = star2 && xabs <= Base<R>::thr;
+  o.fallback = !common;
+  if (!__all(common)) {
+    if (!common) rare_sums(v, astar, star2, xabs, Dv, Ds, Gs);
   }
   // f = f^eq to rounding: the paper leaves alpha free there; take alpha_*.
   const bool guard = !has_pos || !(Dv > Prec<R>::guard * v.rho);
@@ -241,15 +301,22 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(const SiteView<D, S, R>& v, 
   return o;
 }
 
+// Per-thread diagnostics of the sites a thread updated.
 struct Acc {
-  int c[8];
-  double amin, amax, rho, j[3], H;
+  uint32_t c[kNumCounts];  // wavefront totals (uniform), from ballots
+  int iters;               // per lane (root-solver modes)
+  float amin, amax;        // per lane
+  double rho, j[3], H;     // per lane (ELBM_DIAG_SUMS)
   __device__ void init() {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c[k] = 0;
+    for (int k = 0; k < kNumCounts; ++k) c[k] = 0;
+    iters = 0;
     amin = INFINITY;
     amax = -INFINITY;
     rho = j[0] = j[1] = j[2] = H = 0.0;
+  }
+  __device__ __forceinline__ void count(int k, bool pred) {
+    c[k] += (uint32_t)__popcll(__ballot(pred));
   }
 };
 
@@ -263,51 +330,80 @@ __device__ __forceinline__ int wsumi(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
-__device__ __forceinline__ double wmin(double v) {
+__device__ __forceinline__ float wminf(float v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
   return v;
 }
-__device__ __forceinline__ double wmax(double v) {
+__device__ __forceinline__ float wmaxf(float v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;
 }
 
-// Wavefront reductions, then a fixed-order sum over the block's wavefronts:
-// the record is a deterministic function of the block's sites.
-__device__ void store_partial(const Acc& a, void* partials, int slot) {
-  __shared__ int sc[kBlock / 64][8];
-  __shared__ double sd[kBlock / 64][8];
+// Wavefront reductions, then a fixed-order combination over the block's
+// wavefronts: each record is a deterministic function of the block's sites.
+template <bool ITERS>
+__device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
+  constexpr int NW = kBlock / 64;
+  __shared__ uint32_t sc[NW][kNumCounts];
+  __shared__ float sa[NW][2];
+  __shared__ double ss[NW][5];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int c[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) c[k] = wsumi(a.c[k]);
-  const double v0 = wmin(a.amin), v1 = wmax(a.amax), v2 = wsum(a.rho), v3 = wsum(a.j[0]),
-               v4 = wsum(a.j[1]), v5 = wsum(a.j[2]), v6 = wsum(a.H);
+  const bool sums = (d.diag & kDiagSums) != 0;
+  uint32_t it = 0;
+  if constexpr (ITERS) it = (uint32_t)wsumi(a.iters);
+  const float mn = wminf(a.amin), mx = wmaxf(a.amax);
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (sums) {
+    v[0] = wsum(a.rho);
+    v[1] = wsum(a.j[0]);
+    v[2] = wsum(a.j[1]);
+    v[3] = wsum(a.j[2]);
+    v[4] = wsum(a.H);
+  }
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) sc[w][k] = c[k];
-    sd[w][0] = v0; sd[w][1] = v1; sd[w][2] = v2; sd[w][3] = v3;
-    sd[w][4] = v4; sd[w][5] = v5; sd[w][6] = v6; sd[w][7] = 0.0;
+    for (int k = 0; k < kNumCounts; ++k) sc[w][k] = a.c[k];
+    if (ITERS) sc[w][kCntIters] = it;
+    sa[w][0] = mn;
+    sa[w][1] = mx;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) ss[w][k] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    Partial p;
-    for (int k = 0; k < 8; ++k) {
-      int64_t s = 0;
-      for (int q = 0; q < kBlock / 64; ++q) s += sc[q][k];
-      p.cnt[k] = s;
+    CountRec r;
+    for (int k = 0; k < kNumCounts; ++k) {
+      uint32_t s = 0;
+      for (int q = 0; q < NW; ++q) s += sc[q][k];
+      r.cnt[k] = s;
     }
-    p.amin = sd[0][0]; p.amax = sd[0][1];
-    p.rho = sd[0][2]; p.jx = sd[0][3]; p.jy = sd[0][4]; p.jz = sd[0][5]; p.H = sd[0][6];
-    for (int q = 1; q < kBlock / 64; ++q) {
-      p.amin = fmin(p.amin, sd[q][0]);
-      p.amax = fmax(p.amax, sd[q][1]);
-      p.rho += sd[q][2]; p.jx += sd[q][3]; p.jy += sd[q][4]; p.jz += sd[q][5]; p.H += sd[q][6];
+    r.amin = sa[0][0];
+    r.amax = sa[0][1];
+    for (int q = 1; q < NW; ++q) {
+      r.amin = fminf(r.amin, sa[q][0]);
+      r.amax = fmaxf(r.amax, sa[q][1]);
     }
-    p.pad = 0.0;
-    reinterpret_cast<Partial*>(partials)[slot] = p;
+    r.pad[0] = r.pad[1] = 0;
+    reinterpret_cast<CountRec*>(d.counts)[slot] = r;
+    if (sums) {
+      SumRec q;
+      q.rho = ss[0][0];
+      q.j[0] = ss[0][1];
+      q.j[1] = ss[0][2];
+      q.j[2] = ss[0][3];
+      q.H = ss[0][4];
+      for (int k = 1; k < NW; ++k) {
+        q.rho += ss[k][0];
+        q.j[0] += ss[k][1];
+        q.j[1] += ss[k][2];
+        q.j[2] += ss[k][3];
+        q.H += ss[k][4];
+      }
+      q.pad[0] = q.pad[1] = q.pad[2] = 0.0;
+      reinterpret_cast<SumRec*>(d.sums)[slot] = q;
+    }
   }
 }
 
@@ -328,18 +424,24 @@ __device__ __forceinline__ void st_nt(T* base, uint32_t boff, T v) {
   __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff));
 }
 
+// One site: pull, moments, equilibrium, alpha, collision, store.  `live` is
+// false for the padding lanes of the last tile: they compute on site 0 so
+// that wavefront-wide votes see ordinary values, and store nothing.
 template <int D, class S, int MODE, class R>
 __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::T* __restrict__ src,
                                             typename S::T* __restrict__ dst, uint32_t s,
-                                            Acc& acc, int diag) {
+                                            bool live, Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
   constexpr uint32_t es = sizeof(T);
   const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
+  if (!live) s = 0;
   uint32_t x, y, z;
   if constexpr (D == 1) {
-    x = s; y = 0; z = 0;
+    x = s;
+    y = 0;
+    z = 0;
   } else {
     const uint32_t row = qdiv(s, 1.0 / (double)d.nx);
     x = s - row * nx;
@@ -352,8 +454,16 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
   const uint32_t nxy = nx * ny;
   const uint32_t zs[3] = {z * nxy, (z == 0 ? nz - 1 : z - 1) * nxy, (z == nz - 1 ? 0 : z + 1) * nxy};
 
-  SiteView<D, S, R> v;
+  Site<D, S, R> v;
   const int64_t pitch = d.pitch;
+  v.src = src;
+  v.pitch = pitch;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v.xs[k] = xs[k];
+    v.ys[k] = ys[k];
+    v.zs[k] = zs[k];
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t off = zs[L::dg(i, 2)] + ys[L::dg(i, 1)] + xs[L::dg(i, 0)];
@@ -361,80 +471,103 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
   }
   v.rho_ref = (R)d.rho_ref;
 
-  // moments
+  // Moments, summed per x-row of directions first: for each (c_y, c_z) the
+  // three directions c_x = 0, +1, -1 give a row sum and an x-momentum term.
   R rho = R(0), j[3] = {R(0), R(0), R(0)};
+  {
+    R rs[3][3], rx[3][3];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R gi = v.g(i);
-    rho += gi;
+    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz)
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
-      if (L::c(i, a) == 1) j[a] += gi;
-      if (L::c(i, a) == -1) j[a] -= gi;
+      for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+        const int i0 = 9 * dz + 3 * dy;
+        const R g0 = v.g(i0), gp = v.g(i0 + 1), gm = v.g(i0 + 2);
+        rs[dy][dz] = g0 + (gp + gm);
+        rx[dy][dz] = gp - gm;
+      }
+#pragma unroll
+    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) {
+      R cz = R(0);
+#pragma unroll
+      for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+        cz += rs[dy][dz];
+        j[0] += rx[dy][dz];
+      }
+      rho += cz;
+      if (D > 2) j[2] += (dz == 1) ? cz : (dz == 2 ? -cz : R(0));
+    }
+    if (D > 1) {
+#pragma unroll
+      for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) j[1] += rs[1][dz] - rs[2][dz];
     }
   }
   const R irho = R(1) / rho;
-  R u[3] = {j[0] * irho, j[1] * irho, j[2] * irho};
   v.rho = rho;
   v.irho = irho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v.u[a] = j[a] * irho;
   const R beta = (R)d.beta;
   const uint32_t so = s * es;  // own site: dst_i(x) is written here
   R alpha = R(2);
+  R ftmin;
 
   if constexpr (MODE == kBGK) {
     // LBGK: alpha = 2 with the second-order polynomial equilibrium.
+    const R* u = v.u;
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R tb = R(2) * beta;
-    int neg = 0, nonfin = 0;
+    ftmin = R(INFINITY);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R cu = R(L::c(i, 0)) * u[0] + R(L::c(i, 1)) * u[1] + R(L::c(i, 2)) * u[2];
       const R fe = R(L::W(i)) * rho * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
       const R gi = v.g(i);
       const R ft = gi + tb * (fe - gi);
-      if (diag & kDiagCounts) {
-        neg += ft < R(0);
-        nonfin += !isfinite(ft);
-      }
-      st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      ftmin = fmin(ftmin, ft);
+      if (live) st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
-      acc.c[5] += neg;
-      acc.c[6] += nonfin;
+      acc.count(kCntNeg, live && ftmin < R(0));
+      acc.count(kCntNonfinite, live && !isfinite(rho * u[0] * u[1] * u[2] + rho));
     }
   } else {
-    v.eq.build(u);
+    Equilibrium<R, D> eq;
+    eq.build(v.u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v.e[a][c] = eq.e[a][c];
+        v.ie[a][c] = eq.ie[a][c];
+      }
     const AlphaOut<R> ao = choose_alpha<MODE>(v, d);
     alpha = ao.alpha;
     // Eq. (1): f~_i = f_i + alpha beta (f^eq_i - f_i)
     const R ab = alpha * beta;
     const R r = opaque(v.rho);
-    int neg = 0, nonfin = 0;
+    ftmin = R(INFINITY);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R gi = v.g(i);
       const R ft = fma(ab, v.fe(i, r) - gi, gi);
-      if (diag & kDiagCounts) {
-        neg += ft < R(0);
-        nonfin += !isfinite(ft);
-      }
-      st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      ftmin = fmin(ftmin, ft);
+      if (live) st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
-      acc.c[0] += ao.accepted2;
-      acc.c[1] += ao.astar_lt2;
-      acc.c[2] += alpha < R(2);
-      acc.c[3] += ao.guard;
-      acc.c[4] += ao.fallback;
-      acc.c[5] += neg;
-      acc.c[6] += nonfin;
-      acc.c[7] += ao.iters;
-      if (diag & kDiagEntropy) {
+      acc.count(kCntAccept2, live && ao.accepted2);
+      acc.count(kCntAstarLt2, live && ao.astar_lt2);
+      acc.count(kCntAlphaLt2, live && alpha < R(2));
+      acc.count(kCntGuard, live && ao.guard);
+      acc.count(kCntFallback, live && ao.fallback);
+      acc.count(kCntNeg, live && ftmin < R(0));
+      acc.count(kCntNonfinite, live && !isfinite(rho * alpha * v.u[0] * v.u[1] * v.u[2] + rho));
+      if (live) acc.iters += ao.iters;
+      if (live && (diag & kDiagSums)) {
         // H(f) = H(f^eq) + D, H(f^eq) = rho [ln rho + sum_a (ln A_a + u_a ln z_a)]
         double h = log((double)rho);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const double ua = (double)u[a];
+          const double ua = (double)v.u[a];
           const double sa = sqrt(1.0 + 3.0 * ua * ua);
           h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
         }
@@ -442,13 +575,15 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
       }
     }
   }
-  if (diag & kDiagAlpha) d.alpha[s] = (double)alpha;
-  if (diag & kDiagCounts) {
-    acc.amin = fmin(acc.amin, (double)alpha);
-    acc.amax = fmax(acc.amax, (double)alpha);
-    acc.rho += (double)rho;
+  if (live && (diag & kDiagAlpha)) d.alpha[s] = (double)alpha;
+  if (live && (diag & kDiagCounts)) {
+    acc.amin = fminf(acc.amin, (float)alpha);
+    acc.amax = fmaxf(acc.amax, (float)alpha);
+    if (diag & kDiagSums) {
+      acc.rho += (double)rho;
 #pragma unroll
-    for (int a = 0; a < D; ++a) acc.j[a] += (double)j[a];
+      for (int a = 0; a < D; ++a) acc.j[a] += (double)j[a];
+    }
   }
 }
 
@@ -473,11 +608,13 @@ __global__ void __launch_bounds__(kBlock) k_step(const BatchArgs args) {
   const uint32_t tile = (lb & 7u) * chunk + (lb >> 3);
   const int diag = d.diag;
   const uint32_t N = (uint32_t)d.nx * (uint32_t)d.ny * (uint32_t)d.nz;
+  if (tile * kBlock >= N && !(diag & kDiagCounts)) return;  // padding workgroup
   const uint32_t s = tile * kBlock + threadIdx.x;
   Acc acc;
   acc.init();
-  if (s < N) site_update<D, S, MODE, R>(d, src, dst, s, acc, diag);
-  if (diag & kDiagCounts) store_partial(acc, d.partials, (int)lb);
+  if (tile * kBlock < N) site_update<D, S, MODE, R>(d, src, dst, s, s < N, acc, diag);
+  if (diag & kDiagCounts)
+    store_records<MODE == kNewton || MODE == kBisect || MODE == kSecant>(acc, d, (int)lb);
 }
 
 template <int D, class S, int MODE, class R>

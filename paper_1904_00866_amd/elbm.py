@@ -21,7 +21,7 @@ D1Q3, D2Q9, D3Q27 = 1, 2, 3
 LATTICES = {"d1q3": D1Q3, "d2q9": D2Q9, "d3q27": D3Q27}
 MODES = {"closed": 0, "newton": 1, "bisect": 2, "bgk": 3, "secant": 4}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
-DIAG_ALPHA, DIAG_COUNTS, DIAG_ENTROPY = 1, 2, 4
+DIAG_ALPHA, DIAG_COUNTS, DIAG_SUMS = 1, 2, 4
 STATUS = {0: "ELBM_OK", -1: "ELBM_EINVAL", -2: "ELBM_EDEVICE", -3: "ELBM_ENOMEM",
           -4: "ELBM_ESTATE", -5: "ELBM_EUNSUPPORTED"}
 EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_populations",

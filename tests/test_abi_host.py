@@ -65,7 +65,7 @@ def test_default_config_and_state_bytes():
     (dict(beta=0.0), "beta"),
     (dict(mode="newton", fp64=False), "FP32 arithmetic"),
     (dict(storage="f64", fp64=False), "FP64 storage"),
-    (dict(diag=elbm.DIAG_ENTROPY), "ENTROPY"),
+    (dict(diag=elbm.DIAG_SUMS), "SUMS"),
     (dict(diag=64), "diagnostics"),
     (dict(storage="f16dev", rho_ref=0.0), "rho_ref"),
     (dict(mode="secant", secant_iters=0), "secant"),

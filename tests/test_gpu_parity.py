@@ -46,7 +46,7 @@ def test_one_step_fp64(gpu, orc, D, mode):
     N = int(np.prod(shape))
     f0 = _random_state(D, N, seed=10 * D + len(mode))
     sim = _sim(gpu, D, shape, f0, storage="f64", beta=0.97, mode=mode,
-               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS)
+               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS | gpu.DIAG_SUMS)
     assert np.array_equal(sim.populations().cpu().numpy(), f0)
     sim.step(1)
     fg = sim.populations().cpu().numpy()
@@ -188,7 +188,7 @@ def test_d3q27_multistep_fp64_ragged(gpu, orc):
     N = int(np.prod(shape))
     rho, u = Wk.random_velocity_field(3, N, 0.05, seed=8)
     sim = _sim(gpu, 3, shape, rho=rho, u=u, storage="f64", beta=0.9,
-               diag=gpu.DIAG_COUNTS | gpu.DIAG_ENTROPY)
+               diag=gpu.DIAG_COUNTS | gpu.DIAG_SUMS)
     cfg = _ocfg(orc, 3, shape, beta=0.9, nthreads=8)
     fo = orc.init(cfg, rho, u)
     Hs = []
