@@ -114,9 +114,10 @@ typedef struct {
   double root_tol;       /* bisection window; the paper uses 1e-13        */
   int32_t root_max_iter; /* cap for Newton / bisection iterations (>= 1)  */
   uint32_t diag;         /* ELBM_DIAG_* mask                              */
-  int32_t plane_pad;     /* extra elements between population planes;
+  int32_t plane_pad;     /* extra elements after each population plane
+                            (a plane holds N rounded up to 256 sites);
                             -1 selects the library default                */
-  int32_t reserved;
+  int32_t reserved;      /* must be 0                                     */
 } elbm_config;
 
 /* Per-step diagnostics of the most recent step (ELBM_DIAG_COUNTS).  In

@@ -96,6 +96,7 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   if ((c->diag & ELBM_DIAG_SUMS) && !(c->diag & ELBM_DIAG_COUNTS))
     return fail(ELBM_EINVAL, "ELBM_DIAG_SUMS needs ELBM_DIAG_COUNTS");
   if (c->plane_pad < -1) return fail(ELBM_EINVAL, "plane_pad must be >= -1");
+  if (c->reserved != 0) return fail(ELBM_EINVAL, "reserved must be 0");
   if (!step_launcher(D, c->storage, c->alpha_mode, c->alpha_fp64))
     return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
 
@@ -103,20 +104,27 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   L->Q = D == 1 ? 3 : D == 2 ? 9 : 27;
   L->esize = es;
   L->N = N;
-  // Planes start on 256-byte boundaries; the default adds one 256-byte
-  // block so that equal sites of different planes are not a multiple of a
-  // large power of two apart.
+  // One workgroup per tiles_per_block() tiles of kBlock sites, rounded up to a
+  // multiple of 8 (the kernel's XCD-aware tile order needs it).  The count
+  // depends only on the box, so per-workgroup diagnostics sum in the same
+  // order wherever and however the simulation is stepped.
+  const int64_t tpb = tiles_per_block(es);
+  const int64_t ntiles = (N + kBlock - 1) / kBlock;
+  const int64_t units = (ntiles + tpb - 1) / tpb;
+  L->nblocks = int((units + 7) / 8 * 8);
+  // A plane holds the N sites, padding up to the next multiple of kBlock
+  // sites (the stores of the last tile's idle lanes land there), then
+  // plane_pad more elements, rounded to 256 bytes.  The default pad is one
+  // 256-byte block, so that equal sites of different planes are not a
+  // multiple of a large power of two apart.
   const int64_t per256 = 256 / es;
   const int64_t pad = c->plane_pad >= 0 ? c->plane_pad : per256;
-  L->pitch = int64_t(align_up(size_t(N + pad), size_t(per256)));
+  const int64_t padded = L->nblocks * tpb * kBlock;
+  L->pitch = int64_t(align_up(size_t(padded + pad), size_t(per256)));
   // The kernels address a plane with 32-bit byte offsets.
   if (uint64_t(L->pitch) * uint64_t(es) >= (uint64_t(1) << 32))
     return fail(ELBM_EINVAL, "%lld sites of %d bytes exceed the 4 GiB plane limit",
                 (long long)N, es);
-  // One workgroup per tile of kBlock sites, rounded up to a multiple of 8
-  // (the kernel's XCD-aware tile order needs it).
-  const int64_t ntiles = (N + kBlock - 1) / kBlock;
-  L->nblocks = int((ntiles + 7) / 8 * 8);
   size_t off = 0;
   const size_t bufbytes = align_up(size_t(L->Q) * size_t(L->pitch) * es, kAlign);
   L->off_buf[0] = off;
@@ -124,7 +132,7 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   L->off_buf[1] = off;
   off += bufbytes;
   L->off_alpha = off;
-  if (c->diag & ELBM_DIAG_ALPHA) off += align_up(size_t(N) * 8, kAlign);
+  if (c->diag & ELBM_DIAG_ALPHA) off += align_up(size_t(padded) * 8, kAlign);
   L->off_counts = off;
   if (c->diag & ELBM_DIAG_COUNTS) off += align_up(size_t(L->nblocks) * kCountBytes, kAlign);
   L->off_sums = off;
@@ -199,6 +207,8 @@ SimDesc desc_of(const elbm_sim* s, int block_begin) {
   d.beta = s->cfg.beta;
   d.rho_ref = s->cfg.rho_ref;
   d.root_tol = s->cfg.root_tol;
+  d.inv_nx = 1.0 / double(s->cfg.nx);
+  d.inv_ny = 1.0 / double(s->cfg.ny);
   d.nx = s->cfg.nx;
   d.ny = s->cfg.ny;
   d.nz = s->cfg.nz;

@@ -8,6 +8,11 @@
 namespace elbm {
 
 constexpr int kBlock = 256;        // threads per workgroup of the step kernel
+
+// Tiles of kBlock sites per step workgroup: two for 2- and 4-byte storage
+// (the second tile's loads overlap the first tile's arithmetic), one for
+// FP64 storage (two would not fit the register file at two waves per SIMD).
+constexpr int tiles_per_block(int elem_bytes) { return elem_bytes < 8 ? 2 : 1; }
 constexpr int kMaxBatch = 16;      // simulations per batched launch
 constexpr int kCountBytes = 48;    // per-workgroup counts record
 constexpr int kSumBytes = 64;      // per-workgroup sums record
@@ -33,6 +38,7 @@ struct SimDesc {
   void* sums;       // nblocks SumRec records, or nullptr
   int64_t pitch;
   double beta, rho_ref, root_tol;
+  double inv_nx, inv_ny;     // 1/nx, 1/ny for the site-coordinate quotients
   int32_t nx, ny, nz, rows;  // rows = ny * nz x-rows of nx sites
   int32_t nblocks;           // workgroups given to this simulation
   int32_t block_begin;       // first workgroup of this simulation

@@ -75,9 +75,18 @@ struct Codec {
     if constexpr (S::dev) return W * (rho_ref + (R)v);
     else return (R)v;
   }
+  // FP16 is formed from the FP32 value (there is no direct FP64 -> FP16
+  // conversion instruction): round to nearest even twice, which differs from
+  // a single rounding only for FP64 values within 2^-24 of an FP16 tie.
   __device__ static __forceinline__ typename S::T enc(R f, R invW, R rho_ref) {
-    if constexpr (S::dev) return (typename S::T)(f * invW - rho_ref);
-    else return (typename S::T)f;
+    using T = typename S::T;
+    if constexpr (S::dev) {
+      const R sdev = f * invW - rho_ref;
+      if constexpr (sizeof(T) == 2) return (T)(float)sdev;
+      else return (T)sdev;
+    } else {
+      return (T)f;
+    }
   }
 };
 

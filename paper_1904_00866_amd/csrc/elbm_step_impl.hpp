@@ -24,6 +24,10 @@
 #include "elbm_internal.hpp"
 #include "elbm_site.hpp"
 
+#ifndef ELBM_LB_EXTRA
+#define ELBM_LB_EXTRA
+#endif
+
 namespace elbm {
 
 // Keeps a value in registers but hides it from the optimiser, so that
@@ -40,25 +44,77 @@ __device__ __forceinline__ R sel3(const R (&a)[3], int d) {
   return d == 0 ? a[0] : (d == 1 ? a[1] : a[2]);
 }
 
-// Lengths of the common-path series and its validity bound: truncating
-// E and O after K terms changes alpha by about 2 x^(2K+1)/((2K+3)(2K+2)),
-// below 2^-53 (FP64) / 2^-24 (FP32) for max_i |x_i| up to the bound.
+// Series lengths of the three tiers and their validity bounds on
+// max_i |x_i|: truncating E and O after K terms changes alpha by about
+// 2 x^(2K+1)/((2K+3)(2K+2)), kept below 2^-53 (FP64) or 2^-24 (FP32).
+//   common tier: K terms, one unrolled pass fused with the x range;
+//   middle tier: KM terms, one more unrolled pass for wavefronts that need it;
+//   rare tier:   KL terms (or the log1p forms beyond thrL, or when
+//                alpha_* < 2), a rolled loop for the lanes that need it.
 template <class R>
 struct Base;
+#ifndef ELBM_BASE_K
+#define ELBM_BASE_K 3
+#endif
 template <>
 struct Base<double> {
-  static constexpr int K = 3;
-  static constexpr double thr = 8.5e-3;
-  static constexpr int KL = 14;  // long series of the rare path
+  static constexpr int K = ELBM_BASE_K;
+  // 2^-53 bound of the common tier for K = 2, 3, 4
+  static constexpr double thr = K <= 2 ? 1.15e-3 : (K == 3 ? 8.5e-3 : 0.025);
+  static constexpr int KM = 4;
+  static constexpr double thrM = 0.025;
+  static constexpr int KL = 14;
   static constexpr double thrL = 0.30;
 };
 template <>
 struct Base<float> {
   static constexpr int K = 2;
   static constexpr float thr = 0.06f;
+  static constexpr int KM = 4;
+  static constexpr float thrM = 0.24f;
   static constexpr int KL = 7;
   static constexpr float thrL = 0.30f;
 };
+
+// Quotient of s < 2^31 by n < 2^20 through one FP64 multiply: (s + 1/2)/n is
+// at least 1/(2n) away from an integer, far more than the rounding error.
+__device__ __forceinline__ uint32_t qdiv(uint32_t s, double inv_n) {
+  return (uint32_t)(((double)s + 0.5) * inv_n);
+}
+
+// Source coordinates of one site for digit 0 (c = 0), 1 (c = +1: pull from
+// -1) and 2 (c = -1), as element offsets: x, y * nx, z * nx * ny.
+struct Where {
+  uint32_t xs[3], ys[3], zs[3];
+};
+
+template <int D>
+__device__ __forceinline__ Where locate(const SimDesc& d, uint32_t s) {
+  const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
+  uint32_t x, y, z;
+  if constexpr (D == 1) {
+    x = s;
+    y = 0;
+    z = 0;
+  } else {
+    const uint32_t row = qdiv(s, d.inv_nx);
+    x = s - row * nx;
+    z = (D == 3) ? qdiv(row, d.inv_ny) : 0u;
+    y = row - z * ny;
+  }
+  Where w;
+  w.xs[0] = x;
+  w.xs[1] = x == 0 ? nx - 1 : x - 1;
+  w.xs[2] = x == nx - 1 ? 0 : x + 1;
+  w.ys[0] = y * nx;
+  w.ys[1] = (y == 0 ? ny - 1 : y - 1) * nx;
+  w.ys[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+  const uint32_t nxy = nx * ny;
+  w.zs[0] = z * nxy;
+  w.zs[1] = (z == 0 ? nz - 1 : z - 1) * nxy;
+  w.zs[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+  return w;
+}
 
 // One site's loaded populations, density and equilibrium factors.
 template <int D, class S, class R>
@@ -71,10 +127,14 @@ struct Site {
   R u[3];
   R e[3][3];   // e[a][d]  = w(c) A_a z_a^c   (digit d of c)
   R ie[3][3];  // ie[a][d] = 1 / e[a][d]
+  R f01[3][3]; // rho e[0][dx] e[1][dy]:  f^eq_i = f01[dx][dy] e[2][dz]
+  R r01[3][3]; // ie[0][dx] ie[1][dy] / rho: 1/f^eq_i = r01[dx][dy] ie[2][dz]
   // where the populations came from, for the loops of the rare paths
   const T* src;
   int64_t pitch;
-  uint32_t xs[3], ys[3], zs[3];
+  uint32_t site;
+  const SimDesc* desc;
+  Where w;  // filled by locate_rare() before a rare-path loop
 
   // -- unrolled accessors (compile-time i) --------------------------------
   // The loaded value passes through opaque() so that its conversion is redone
@@ -82,12 +142,36 @@ struct Site {
   __device__ __forceinline__ R g(int i) const {
     return Codec<S, R>::dec(opaque(raw[i]), R(L::W(i)), rho_ref);
   }
-  __device__ __forceinline__ R fe(int i, R r) const {
-    return r * (e[0][L::dg(i, 0)] * e[1][L::dg(i, 1)]) * e[2][L::dg(i, 2)];
+  // Each pass takes opaque copies of the z-axis factors, so that f^eq_i and
+  // 1/f^eq_i (one product each) are recomputed per pass, not kept.
+  struct Pass {
+    R e2[3], ie2[3];
+  };
+  __device__ __forceinline__ Pass pass() const {
+    Pass p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      p.e2[k] = opaque(e[2][k]);
+      p.ie2[k] = opaque(ie[2][k]);
+    }
+    return p;
   }
-  __device__ __forceinline__ R x(int i, R ir) const {
-    const R ri = ir * (ie[0][L::dg(i, 0)] * ie[1][L::dg(i, 1)]) * ie[2][L::dg(i, 2)];
-    return fma(g(i), ri, R(-1));
+  __device__ __forceinline__ R fe(int i, const Pass& p) const {
+    const R q = f01[L::dg(i, 0)][L::dg(i, 1)];
+    return D > 2 ? q * p.e2[L::dg(i, 2)] : q;
+  }
+  __device__ __forceinline__ R x(int i, const Pass& p) const {
+    const R q = r01[L::dg(i, 0)][L::dg(i, 1)];
+    return fma(g(i), D > 2 ? q * p.ie2[L::dg(i, 2)] : q, R(-1));
+  }
+  __device__ __forceinline__ void fold() {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        f01[a][b] = rho * (e[0][a] * e[1][b]);
+        r01[a][b] = irho * (ie[0][a] * ie[1][b]);
+      }
   }
 
   // -- loop accessors (run-time, wavefront-uniform i) -----------------------
@@ -98,7 +182,7 @@ struct Site {
     const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
     const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
     const R W = R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0) / R(L::den());
-    const uint32_t off = sel3(zs, dz) + sel3(ys, dy) + sel3(xs, dx);
+    const uint32_t off = sel3(w.zs, dz) + sel3(w.ys, dy) + sel3(w.xs, dx);
     const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(src + (int64_t)i * pitch) +
                                             off * (uint32_t)sizeof(T));
     const R gi = Codec<S, R>::dec(*p, W, rho_ref);
@@ -183,39 +267,74 @@ struct AlphaOut {
 
 // The choice of alpha at one site (all lanes of the wavefront call it).
 template <int MODE, int D, class S, class R>
-__device__ __forceinline__ AlphaOut<R> choose_alpha(const Site<D, S, R>& v, const SimDesc& d) {
+__device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimDesc& d) {
   constexpr int Q = Site<D, S, R>::Q;
   AlphaOut<R> o;
-  // Common pass: x_i, the x range, and the K-term series sums together.
+  // The root solvers need alpha_max on every lane; the closed form and the
+  // secant need it only where alpha_* < 2, which the tiers below detect.
+  constexpr bool kXmax = (MODE == kNewton || MODE == kBisect);
+  if constexpr (MODE == kNewton || MODE == kBisect || MODE == kSecant) v.w = locate<D>(d, v.site);
+  // Common tier: x_i, max|x_i| and the K-term series sums in one pass.
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   {
-    const R r = opaque(v.rho), ir = opaque(v.irho);
+  const auto P = v.pass();
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R xi = v.x(i, P);
+    if (kXmax) xmax = fmax(xmax, xi);
+    xabs = fmax(xabs, fabs(xi));
+    R E, O;
+    series_EO<R, Base<R>::K>(xi, E, O);
+    const R fi = v.fe(i, P);
+    sE = fma(fi, E, sE);
+    sO = fma(fi, O, sO);
+  }
+  }
+  // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
+  // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
+  R Dv = sE - sO, Ds = sE + sO, Gs = R(2) * sO;
+  // max|x| <= thrM < 1 implies max x <= 1, i.e. alpha_* = 2.
+  const bool common = xabs <= Base<R>::thr;
+  const bool mid = !common && xabs <= Base<R>::thrM;
+  const bool rare = !(xabs <= Base<R>::thrM);
+  if (__any(mid)) {
+    R mE = R(0), mO = R(0);
+    const auto P = v.pass();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const R xi = v.x(i, ir);
-      xmax = fmax(xmax, xi);
-      xabs = fmax(xabs, fabs(xi));
       R E, O;
-      series_EO<R, Base<R>::K>(xi, E, O);
-      const R fi = v.fe(i, r);
-      sE = fma(fi, E, sE);
-      sO = fma(fi, O, sO);
+      series_EO<R, Base<R>::KM>(v.x(i, P), E, O);
+      const R fi = v.fe(i, P);
+      mE = fma(fi, E, mE);
+      mO = fma(fi, O, mO);
+    }
+    if (mid) {
+      Dv = mE - mO;
+      Ds = mE + mO;
+      Gs = R(2) * mO;
+    }
+  }
+  if (__any(rare) && !kXmax) v.w = locate<D>(d, v.site);
+  if (rare && !kXmax) {
+    xmax = R(-1);
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      R xi, fi;
+      v.xfe(i, xi, fi);
+      xmax = fmax(xmax, xi);
     }
   }
   // alpha_max = min over {f^eq_i < f_i} of f_i/(f_i - f^eq_i) = 1 + 1/max_i x_i
   // (definition after Eq. (7)); alpha_* = min(2, alpha_max) (Eq. (8)), and
-  // alpha_* = 2 exactly when max_i x_i <= 1.
-  const bool has_pos = xmax > R(0);
+  // alpha_* = 2 exactly when max_i x_i <= 1.  Outside the rare tier (and the
+  // root solvers) xmax is not formed and alpha_* = 2.
+  const bool has_pos = (rare || kXmax) ? xmax > R(0) : true;
   const R amax = has_pos ? R(1) + R(1) / xmax : R(INFINITY);
-  const bool star2 = !(xmax > R(1));
+  const bool star2 = (rare || kXmax) ? !(xmax > R(1)) : true;
   const R astar = star2 ? R(2) : amax;
-  // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
-  // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
-  R Dv = sE - sO, Ds = sE + sO, Gs = R(2) * sO;
-  const bool common = star2 && xabs <= Base<R>::thr;
-  o.fallback = !common;
-  if (!__all(common)) {
-    if (!common) rare_sums(v, astar, star2, xabs, Dv, Ds, Gs);
+  o.fallback = rare;
+  if (__any(rare)) {
+    if (rare) rare_sums(v, astar, star2, xabs, Dv, Ds, Gs);
   }
   // f = f^eq to rounding: the paper leaves alpha free there; take alpha_*.
   const bool guard = !has_pos || !(Dv > Prec<R>::guard * v.rho);
@@ -407,68 +526,61 @@ __device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
   }
 }
 
-// Quotient of s < 2^31 by n < 2^20 through one FP64 multiply: (s + 1/2)/n is
-// at least 1/(2n) away from an integer, far more than the rounding error.
-__device__ __forceinline__ uint32_t qdiv(uint32_t s, double inv_n) {
-  return (uint32_t)(((double)s + 0.5) * inv_n);
+// Uniform pointer hidden from the optimiser: plane addresses are then
+// formed per tile (scalar adds) instead of Q of them being hoisted out of the
+// tile loop into scalar registers.
+template <class P>
+__device__ __forceinline__ P opaque_s(P p) {
+  asm volatile("" : "+s"(p));
+  return p;
 }
 
-// Byte-offset load/store from a uniform plane base: the offset stays a
-// 32-bit unsigned VGPR so the address is SGPR base + VGPR offset.
 template <class T>
-__device__ __forceinline__ T ld(const T* base, uint32_t boff) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
-}
-template <class T>
-__device__ __forceinline__ void st_nt(T* base, uint32_t boff, T v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff));
+__device__ __forceinline__ void st_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
 }
 
-// One site: pull, moments, equilibrium, alpha, collision, store.  `live` is
-// false for the padding lanes of the last tile: they compute on site 0 so
-// that wavefront-wide votes see ordinary values, and store nothing.
+// Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
+template <int D, class T>
+__device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32_t s,
+                                          T (&raw)[Lattice<D>::Q]) {
+  using L = Lattice<D>;
+  const Where w = locate<D>(d, s);
+  const char* p = reinterpret_cast<const char*>(opaque_s(src));
+  const int64_t pb = opaque_s(d.pitch * (int64_t)sizeof(T));
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const uint32_t off = w.zs[L::dg(i, 2)] + w.ys[L::dg(i, 1)] + w.xs[L::dg(i, 0)];
+    raw[i] = *reinterpret_cast<const T*>(p + off * (uint32_t)sizeof(T));
+    p += pb;
+  }
+}
+
+// One site from its pulled populations: moments, equilibrium, alpha,
+// collision, store of dst_i(x) at the site's own index.  `live` is false for
+// the padding lanes of the last tile: they compute on the values of site 0
+// (so that wavefront-wide votes see ordinary numbers) and store into the
+// plane padding past N, which every plane has up to the next multiple of
+// kBlock sites and which no step reads.
 template <int D, class S, int MODE, class R>
 __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::T* __restrict__ src,
                                             typename S::T* __restrict__ dst, uint32_t s,
-                                            bool live, Acc& acc, int diag) {
+                                            bool live, const typename S::T (&raw)[Lattice<D>::Q],
+                                            Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
   constexpr uint32_t es = sizeof(T);
-  const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
-  if (!live) s = 0;
-  uint32_t x, y, z;
-  if constexpr (D == 1) {
-    x = s;
-    y = 0;
-    z = 0;
-  } else {
-    const uint32_t row = qdiv(s, 1.0 / (double)d.nx);
-    x = s - row * nx;
-    z = (D == 3) ? qdiv(row, 1.0 / (double)d.ny) : 0u;
-    y = row - z * ny;
-  }
-  // source coordinates for digit 0 (c = 0), 1 (c = +1: pull from -1), 2 (c = -1)
-  const uint32_t xs[3] = {x, x == 0 ? nx - 1 : x - 1, x == nx - 1 ? 0 : x + 1};
-  const uint32_t ys[3] = {y * nx, (y == 0 ? ny - 1 : y - 1) * nx, (y == ny - 1 ? 0 : y + 1) * nx};
-  const uint32_t nxy = nx * ny;
-  const uint32_t zs[3] = {z * nxy, (z == 0 ? nz - 1 : z - 1) * nxy, (z == nz - 1 ? 0 : z + 1) * nxy};
+  const uint32_t sl = live ? s : 0u;  // the site whose values were loaded
 
   Site<D, S, R> v;
   const int64_t pitch = d.pitch;
   v.src = src;
   v.pitch = pitch;
+  v.site = sl;
+  v.desc = &d;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    v.xs[k] = xs[k];
-    v.ys[k] = ys[k];
-    v.zs[k] = zs[k];
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const uint32_t off = zs[L::dg(i, 2)] + ys[L::dg(i, 1)] + xs[L::dg(i, 0)];
-    v.raw[i] = ld(src + (int64_t)i * pitch, off * es);
-  }
+  for (int i = 0; i < Q; ++i) v.raw[i] = raw[i];
   v.rho_ref = (R)d.rho_ref;
 
   // Moments, summed per x-row of directions first: for each (c_y, c_z) the
@@ -507,7 +619,6 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
 #pragma unroll
   for (int a = 0; a < 3; ++a) v.u[a] = j[a] * irho;
   const R beta = (R)d.beta;
-  const uint32_t so = s * es;  // own site: dst_i(x) is written here
   R alpha = R(2);
   R ftmin;
 
@@ -517,6 +628,8 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R tb = R(2) * beta;
     ftmin = R(INFINITY);
+    T* q = opaque_s(dst) + s;
+    const int64_t pe = opaque_s(pitch);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R cu = R(L::c(i, 0)) * u[0] + R(L::c(i, 1)) * u[1] + R(L::c(i, 2)) * u[2];
@@ -524,7 +637,8 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
       const R gi = v.g(i);
       const R ft = gi + tb * (fe - gi);
       ftmin = fmin(ftmin, ft);
-      if (live) st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt(q, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      q += pe;
     }
     if (diag & kDiagCounts) {
       acc.count(kCntNeg, live && ftmin < R(0));
@@ -540,18 +654,24 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
         v.e[a][c] = eq.e[a][c];
         v.ie[a][c] = eq.ie[a][c];
       }
+    v.fold();
     const AlphaOut<R> ao = choose_alpha<MODE>(v, d);
     alpha = ao.alpha;
-    // Eq. (1): f~_i = f_i + alpha beta (f^eq_i - f_i)
+    // Eq. (1): f~_i = f_i + alpha beta (f^eq_i - f_i), in the site
+    // arithmetic's precision; the result is rounded once, into the storage
+    // format.
     const R ab = alpha * beta;
-    const R r = opaque(v.rho);
+    const auto P = v.pass();
     ftmin = R(INFINITY);
+    T* q = opaque_s(dst) + s;
+    const int64_t pe = opaque_s(pitch);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R gi = v.g(i);
-      const R ft = fma(ab, v.fe(i, r) - gi, gi);
+      const R ft = fma(ab, v.fe(i, P) - gi, gi);
       ftmin = fmin(ftmin, ft);
-      if (live) st_nt(dst + (int64_t)i * pitch, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt(q, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      q += pe;
     }
     if (diag & kDiagCounts) {
       acc.count(kCntAccept2, live && ao.accepted2);
@@ -575,7 +695,7 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
       }
     }
   }
-  if (live && (diag & kDiagAlpha)) d.alpha[s] = (double)alpha;
+  if (diag & kDiagAlpha) d.alpha[s] = (double)alpha;
   if (live && (diag & kDiagCounts)) {
     acc.amin = fminf(acc.amin, (float)alpha);
     acc.amax = fmaxf(acc.amax, (float)alpha);
@@ -587,15 +707,21 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
   }
 }
 
-// One workgroup = one tile of kBlock consecutive sites.  Workgroups are
-// issued round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8), so
-// the tile order is permuted to give each XCD one contiguous eighth of the
-// box: neighbouring tiles, which share the cache lines at their x-edges,
-// then run on the same XCD and L2.  Each simulation's workgroup count is a
-// multiple of 8 and starts at a multiple of 8.
+// One workgroup per ELBM_TILES tiles of kBlock consecutive sites; the loads
+// of all its tiles are issued before the first tile's arithmetic, so that
+// the later tiles' memory latency overlaps it.
+//
+// XCD-aware order: workgroups are issued round-robin over the 8 XCDs
+// (workgroup b runs on XCD b mod 8), so the tile order is permuted to give
+// each XCD one contiguous eighth of the box: neighbouring tiles, which share
+// the cache lines at their x-edges, then run on the same XCD and L2.  Each
+// simulation's workgroup count is a multiple of 8 and starts at a multiple
+// of 8.
 template <int D, class S, int MODE, class R>
-__global__ void __launch_bounds__(kBlock) k_step(const BatchArgs args) {
+__global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs args) {
   using T = typename S::T;
+  constexpr int Q = Lattice<D>::Q;
+  constexpr int ELBM_TILES = tiles_per_block(sizeof(T));
   const int b = blockIdx.x;
   int si = 0;
   for (int k = 1; k < args.n; ++k)
@@ -603,16 +729,29 @@ __global__ void __launch_bounds__(kBlock) k_step(const BatchArgs args) {
   const SimDesc& d = args.d[si];
   const T* __restrict__ src = static_cast<const T*>(d.src);
   T* __restrict__ dst = static_cast<T*>(d.dst);
-  const uint32_t lb = (uint32_t)(b - d.block_begin);
-  const uint32_t chunk = (uint32_t)d.nblocks >> 3;
-  const uint32_t tile = (lb & 7u) * chunk + (lb >> 3);
   const int diag = d.diag;
   const uint32_t N = (uint32_t)d.nx * (uint32_t)d.ny * (uint32_t)d.nz;
-  if (tile * kBlock >= N && !(diag & kDiagCounts)) return;  // padding workgroup
-  const uint32_t s = tile * kBlock + threadIdx.x;
+  const uint32_t lb = (uint32_t)(b - d.block_begin);
+  const uint32_t chunk = (uint32_t)d.nblocks >> 3;
+  const uint32_t unit = (lb & 7u) * chunk + (lb >> 3);  // this workgroup's tile group
   Acc acc;
   acc.init();
-  if (tile * kBlock < N) site_update<D, S, MODE, R>(d, src, dst, s, s < N, acc, diag);
+  if (unit * ELBM_TILES * kBlock < N) {
+    T raw[ELBM_TILES][Q];
+#pragma unroll
+    for (int k = 0; k < ELBM_TILES; ++k) {
+      const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
+      load_site<D>(d, src, s < N ? s : 0u, raw[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < ELBM_TILES; ++k) {
+      const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
+      if (k == 0 || (unit * ELBM_TILES + k) * kBlock < N)
+        site_update<D, S, MODE, R>(d, src, dst, s, s < N, raw[k], acc, diag);
+    }
+  } else if (!(diag & kDiagCounts)) {
+    return;  // padding workgroup
+  }
   if (diag & kDiagCounts)
     store_records<MODE == kNewton || MODE == kBisect || MODE == kSecant>(acc, d, (int)lb);
 }
