@@ -75,6 +75,11 @@ struct Codec {
     if constexpr (S::dev) return W * (rho_ref + (R)v);
     else return (R)v;
   }
+  // the same from a value already widened to R
+  __device__ static __forceinline__ R dec_wide(R v, R W, R rho_ref) {
+    if constexpr (S::dev) return W * (rho_ref + v);
+    else return v;
+  }
   // FP16 is formed from the FP32 value (there is no direct FP64 -> FP16
   // conversion instruction): round to nearest even twice, which differs from
   // a single rounding only for FP64 values within 2^-24 of an FP16 tie.
@@ -178,19 +183,59 @@ __device__ __forceinline__ R dlog_clamped(R y) {
   return Prec<R>::log1p_(y < R(-1) ? R(-1) : y);
 }
 
-// Horner in t = x^2 for E(x)/t and O(x)/(x t), K terms each.
+// Truncated series, K terms each, in t = x^2:
+//   E(x) = sum_k c_k t^k, c_k = 1/(2k (2k-1));  O(x) = x sum_k d_k t^k,
+//   d_k = 1/((2k+1) 2k).
+// SeriesK holds E / c_K and O / d_K as monic polynomials: each Horner step
+// then takes one constant, and the constants sit in scalar registers (an
+// FP64 VALU operation can read one scalar operand but no 64-bit literal, so
+// a constant not held in a scalar register costs vector moves at every use).
+// Multiply the sums by series_scale() afterwards.
+template <class R>
+__device__ __forceinline__ R in_sgpr(R v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+template <class R, int K>
+struct SeriesK {
+  R e[K > 1 ? K - 1 : 1], o[K > 1 ? K - 1 : 1];  // e[k-1], o[k-1] for k = 1 .. K-1
+  __device__ __forceinline__ SeriesK() {
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      e[k - 1] = in_sgpr(R((1.0 / ((2.0 * k) * (2.0 * k - 1.0))) /
+                           (1.0 / ((2.0 * K) * (2.0 * K - 1.0)))));
+      o[k - 1] = in_sgpr(R((1.0 / ((2.0 * k + 1.0) * (2.0 * k))) /
+                           (1.0 / ((2.0 * K + 1.0) * (2.0 * K)))));
+    }
+  }
+  __device__ __forceinline__ void eval(R x, R& E, R& O) const {
+    const R t = x * x;
+    R pe = R(1), po = R(1);
+    if constexpr (K >= 2) {
+      pe = t + e[K - 2];
+      po = t + o[K - 2];
+    }
+#pragma unroll
+    for (int k = K - 2; k >= 1; --k) {
+      pe = fma(pe, t, e[k - 1]);
+      po = fma(po, t, o[k - 1]);
+    }
+    E = pe * t;
+    O = po * t * x;
+  }
+};
+
 template <class R, int K>
 __device__ __forceinline__ void series_EO(R x, R& E, R& O) {
-  const R t = x * x;
-  R pe = R(1.0 / ((2.0 * K) * (2.0 * K - 1.0)));
-  R po = R(1.0 / ((2.0 * K + 1.0) * (2.0 * K)));
-#pragma unroll
-  for (int k = K - 1; k >= 1; --k) {
-    pe = pe * t + R(1.0 / ((2.0 * k) * (2.0 * k - 1.0)));
-    po = po * t + R(1.0 / ((2.0 * k + 1.0) * (2.0 * k)));
-  }
-  E = pe * t;
-  O = po * t * x;
+  SeriesK<R, K>().eval(x, E, O);
+}
+
+// (c_K, d_K): the factors that restore series_EO's sums.
+template <class R, int K>
+__device__ __forceinline__ void series_scale(R& cE, R& cO) {
+  cE = R(1.0 / ((2.0 * K) * (2.0 * K - 1.0)));
+  cO = R(1.0 / ((2.0 * K + 1.0) * (2.0 * K)));
 }
 
 }  // namespace elbm

@@ -21,6 +21,8 @@
 // pressure to the common path.
 #pragma once
 
+#include <type_traits>
+
 #include "elbm_internal.hpp"
 #include "elbm_site.hpp"
 
@@ -37,6 +39,28 @@ template <class R>
 __device__ __forceinline__ R opaque(R v) {
   asm volatile("" : "+v"(v));
   return v;
+}
+
+// The stored population widened to the arithmetic type.  FP32 -> FP64 goes
+// through a volatile asm conversion: the compiler can neither merge the
+// conversions of different passes (which would keep Q doubles live) nor needs
+// to copy the source register first, as an opaque() barrier would.
+template <class R, class T>
+__device__ __forceinline__ auto widen(T v) {
+  if constexpr (std::is_same<T, float>::value && std::is_same<R, double>::value) {
+    double d;
+    asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(d) : "v"(v));
+    return d;
+  } else if constexpr (std::is_same<T, _Float16>::value && std::is_same<R, double>::value) {
+    const float f = (float)v;
+    double d;
+    asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(d) : "v"(f));
+    return d;
+  } else if constexpr (std::is_same<T, _Float16>::value) {
+    return (float)v;
+  } else {
+    return v;
+  }
 }
 
 template <class R>
@@ -75,6 +99,30 @@ struct Base<float> {
   static constexpr int KL = 7;
   static constexpr float thrL = 0.30f;
 };
+
+// Plane addressing.  A plane's base is uniform (scalar registers) and a
+// site's byte offset in it a 32-bit vector register, so loads and stores
+// take the scalar-base + vector-offset form.  The buffer base is passed
+// through in_sgpr() once per tile: the Q plane bases are then formed per
+// tile with scalar adds instead of being held (2 Q scalar registers) across
+// the whole kernel; the explicit global address space keeps the accesses
+// global rather than generic.
+using gaddr = uint64_t;
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gaddr plane_base(const T* buf) {
+  return in_sgpr((gaddr)(uintptr_t)buf);
+}
+template <class T>
+__device__ __forceinline__ T ld(gaddr plane, uint32_t boff) {
+  return *(const gptr<T>)(plane + boff);
+}
+template <class T>
+__device__ __forceinline__ void st_nt(gaddr plane, uint32_t boff, T v) {
+  __builtin_nontemporal_store(v, (gptr<T>)(plane + boff));
+}
 
 // Quotient of s < 2^31 by n < 2^20 through one FP64 multiply: (s + 1/2)/n is
 // at least 1/(2n) away from an integer, far more than the rounding error.
@@ -137,10 +185,10 @@ struct Site {
   Where w;  // filled by locate_rare() before a rare-path loop
 
   // -- unrolled accessors (compile-time i) --------------------------------
-  // The loaded value passes through opaque() so that its conversion is redone
-  // in each pass rather than Q converted values being kept live.
+  // The stored value is widened in each pass (cvt_fresh) rather than Q
+  // widened values being kept live across passes.
   __device__ __forceinline__ R g(int i) const {
-    return Codec<S, R>::dec(opaque(raw[i]), R(L::W(i)), rho_ref);
+    return Codec<S, R>::dec_wide(widen<R>(raw[i]), R(L::W(i)), rho_ref);
   }
   // Each pass takes opaque copies of the z-axis factors, so that f^eq_i and
   // 1/f^eq_i (one product each) are recomputed per pass, not kept.
@@ -183,9 +231,9 @@ struct Site {
     const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
     const R W = R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0) / R(L::den());
     const uint32_t off = sel3(w.zs, dz) + sel3(w.ys, dy) + sel3(w.xs, dx);
-    const T* p = reinterpret_cast<const T*>(reinterpret_cast<const char*>(src + (int64_t)i * pitch) +
-                                            off * (uint32_t)sizeof(T));
-    const R gi = Codec<S, R>::dec(*p, W, rho_ref);
+    const T gv = *(const gptr<T>)((gaddr)(uintptr_t)src + (uint64_t)i * (uint64_t)pitch * sizeof(T) +
+                                   off * (uint32_t)sizeof(T));
+    const R gi = Codec<S, R>::dec(gv, W, rho_ref);
     fi = rho * (sel3(e[0], dx) * sel3(e[1], dy)) * sel3(e[2], dz);
     const R ri = irho * (sel3(ie[0], dx) * sel3(ie[1], dy)) * sel3(ie[2], dz);
     xi = fma(gi, ri, R(-1));
@@ -237,6 +285,10 @@ __device__ __forceinline__ void rare_sums(const Site<D, S, R>& v, R astar, bool 
       sE += fi * E;
       sO += fi * O;
     }
+    R cE, cO;
+    series_scale<R, Base<R>::KL>(cE, cO);
+    sE *= cE;
+    sO *= cO;
     Dv = sE - sO;
     Ds = sE + sO;
     Gs = R(2) * sO;
@@ -277,6 +329,7 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   // Common tier: x_i, max|x_i| and the K-term series sums in one pass.
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   {
+  const SeriesK<R, Base<R>::K> ser;
   const auto P = v.pass();
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -284,11 +337,17 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
     if (kXmax) xmax = fmax(xmax, xi);
     xabs = fmax(xabs, fabs(xi));
     R E, O;
-    series_EO<R, Base<R>::K>(xi, E, O);
+    ser.eval(xi, E, O);
     const R fi = v.fe(i, P);
     sE = fma(fi, E, sE);
     sO = fma(fi, O, sO);
   }
+  }
+  {
+    R cE, cO;
+    series_scale<R, Base<R>::K>(cE, cO);
+    sE *= cE;
+    sO *= cO;
   }
   // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
   // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
@@ -299,15 +358,20 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   const bool rare = !(xabs <= Base<R>::thrM);
   if (__any(mid)) {
     R mE = R(0), mO = R(0);
+    const SeriesK<R, Base<R>::KM> ser;
     const auto P = v.pass();
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       R E, O;
-      series_EO<R, Base<R>::KM>(v.x(i, P), E, O);
+      ser.eval(v.x(i, P), E, O);
       const R fi = v.fe(i, P);
       mE = fma(fi, E, mE);
       mO = fma(fi, O, mO);
     }
+    R cE, cO;
+    series_scale<R, Base<R>::KM>(cE, cO);
+    mE *= cE;
+    mO *= cO;
     if (mid) {
       Dv = mE - mO;
       Ds = mE + mO;
@@ -526,33 +590,18 @@ __device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
   }
 }
 
-// Uniform pointer hidden from the optimiser: plane addresses are then
-// formed per tile (scalar adds) instead of Q of them being hoisted out of the
-// tile loop into scalar registers.
-template <class P>
-__device__ __forceinline__ P opaque_s(P p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
-template <class T>
-__device__ __forceinline__ void st_nt(T* p, T v) {
-  __builtin_nontemporal_store(v, p);
-}
-
 // Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
 template <int D, class T>
 __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32_t s,
                                           T (&raw)[Lattice<D>::Q]) {
   using L = Lattice<D>;
   const Where w = locate<D>(d, s);
-  const char* p = reinterpret_cast<const char*>(opaque_s(src));
-  const int64_t pb = opaque_s(d.pitch * (int64_t)sizeof(T));
+  const gaddr base = plane_base(src);
+  const uint64_t pb = (uint64_t)d.pitch * sizeof(T);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const uint32_t off = w.zs[L::dg(i, 2)] + w.ys[L::dg(i, 1)] + w.xs[L::dg(i, 0)];
-    raw[i] = *reinterpret_cast<const T*>(p + off * (uint32_t)sizeof(T));
-    p += pb;
+    raw[i] = ld<T>(base + i * pb, off * (uint32_t)sizeof(T));
   }
 }
 
@@ -628,8 +677,9 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R tb = R(2) * beta;
     ftmin = R(INFINITY);
-    T* q = opaque_s(dst) + s;
-    const int64_t pe = opaque_s(pitch);
+    const uint32_t so = s * es;
+    const gaddr base = plane_base(dst);
+    const uint64_t pb = (uint64_t)pitch * es;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R cu = R(L::c(i, 0)) * u[0] + R(L::c(i, 1)) * u[1] + R(L::c(i, 2)) * u[2];
@@ -637,8 +687,7 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
       const R gi = v.g(i);
       const R ft = gi + tb * (fe - gi);
       ftmin = fmin(ftmin, ft);
-      st_nt(q, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
-      q += pe;
+      st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
       acc.count(kCntNeg, live && ftmin < R(0));
@@ -663,15 +712,18 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
     const R ab = alpha * beta;
     const auto P = v.pass();
     ftmin = R(INFINITY);
-    T* q = opaque_s(dst) + s;
-    const int64_t pe = opaque_s(pitch);
+    const uint32_t so = s * es;
+    const gaddr base = plane_base(dst);
+    const uint64_t pb = (uint64_t)pitch * es;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R gi = v.g(i);
       const R ft = fma(ab, v.fe(i, P) - gi, gi);
       ftmin = fmin(ftmin, ft);
-      st_nt(q, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
-      q += pe;
+      // a private copy of the offset per store keeps the address in the
+      // scalar-base + vector-offset form (otherwise the common offset is
+      // added first and every plane offset costs 64-bit vector arithmetic)
+      st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
       acc.count(kCntAccept2, live && ao.accepted2);
