@@ -49,7 +49,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(workload_key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", f"step_{workload_key.replace('d3q27_', 'd3q27_n')}_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh).get(workload_key)
