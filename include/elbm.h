@@ -205,6 +205,92 @@ const char *elbm_last_error(void);
 elbm_status elbm_step_batch(elbm_sim *const *sims, const int64_t *nsteps,
                             int32_t n);
 
+/* ---- serving: continuous batching of many simulations ------------------
+ *
+ * A server owns a scheduler thread and sub-allocates the states of the
+ * simulations it admits from one caller-provided device memory pool.
+ * Requests are admitted first come, first served, as soon as a slot is free
+ * and the pool has room for the request's state (elbm_state_bytes) plus a
+ * staging copy of its initial fields.  Each scheduling round advances every
+ * resident simulation by up to round_steps steps with batched launches
+ * (elbm_step_batch: one launch per step for all residents of the same
+ * lattice, storage, alpha mode and arithmetic); a request arriving while a
+ * round runs joins at the next round.  Two rounds are kept in flight on the
+ * stream, so admission and completion work on the host overlaps the GPU.
+ * Each resident simulation gives the same bits as stepping it alone.
+ */
+typedef struct elbm_server elbm_server;
+
+typedef struct {
+  void *pool;           /* device memory to sub-allocate (caller-owned,
+                           256-byte aligned, kept until elbm_server_destroy) */
+  size_t pool_bytes;
+  void *hip_stream;     /* stream of all server work (NULL = null stream)   */
+  int32_t max_active;   /* resident simulations at once, >= 1              */
+  int32_t round_steps;  /* steps per scheduling round, >= 1                */
+} elbm_server_config;
+
+typedef struct {
+  elbm_config cfg;      /* as for elbm_init                                  */
+  const double *rho0;   /* HOST, N values; copied by elbm_server_submit      */
+  const double *u0;     /* HOST, D*N values; copied by elbm_server_submit    */
+  int64_t nsteps;       /* >= 0                                              */
+  double *out_rho;      /* device, N values: rho at the end, or NULL         */
+  double *out_u;        /* device, D*N values: u at the end, or NULL         */
+  int32_t keep_state;   /* 1: keep the simulation resident after its last
+                           step, for elbm_server_sim, until
+                           elbm_server_release                               */
+  int32_t reserved;     /* must be 0                                         */
+} elbm_request;
+
+enum { ELBM_REQ_QUEUED = 0, ELBM_REQ_RUNNING = 1, ELBM_REQ_DONE = 2,
+       ELBM_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;        /* ELBM_REQ_*                                        */
+  int32_t reserved;
+  int64_t steps_done;
+  double t_submit;      /* seconds on the server's monotonic clock          */
+  double t_admit;       /* admission (0 while queued)                        */
+  double t_done;        /* completion observed on the host (0 until done)   */
+  size_t footprint;     /* pool bytes held while resident                    */
+} elbm_request_info;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t rounds, launches;
+  int64_t site_updates; /* sum over completed steps of the box sizes         */
+  int64_t max_resident; /* most simulations resident at once                 */
+  double t_first_submit, t_last_done;
+} elbm_server_stats;
+
+/* Create a server; starts its scheduler thread on the current device. */
+elbm_status elbm_server_create(const elbm_server_config *cfg, elbm_server **out);
+
+/* Queue a request (thread-safe, returns at once).  The configuration and the
+ * host fields are checked here (ELBM_EINVAL); a request whose footprint can
+ * never fit the pool is rejected with ELBM_ENOMEM.  *id receives its id. */
+elbm_status elbm_server_submit(elbm_server *srv, const elbm_request *req,
+                               int64_t *id);
+
+/* State and times of a request (HOST info). */
+elbm_status elbm_server_poll(elbm_server *srv, int64_t id, elbm_request_info *info);
+
+/* Block until request id is done or failed, or timeout_s seconds pass
+ * (ELBM_ESTATE on timeout; timeout_s < 0 waits without limit). */
+elbm_status elbm_server_wait(elbm_server *srv, int64_t id, double timeout_s);
+
+/* The simulation of a completed keep_state request (valid until release). */
+elbm_status elbm_server_sim(elbm_server *srv, int64_t id, elbm_sim **sim);
+
+/* Free a completed keep_state request's state. */
+elbm_status elbm_server_release(elbm_server *srv, int64_t id);
+
+elbm_status elbm_server_get_stats(elbm_server *srv, elbm_server_stats *stats);
+
+/* Finish every submitted request, stop the scheduler, free the server. */
+elbm_status elbm_server_destroy(elbm_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -264,8 +264,33 @@ size_t elbm_state_bytes(const elbm_config* cfg) {
   return L.total;
 }
 
-elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* u0,
-                      void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out) {
+}  // extern "C"
+
+namespace elbm {
+
+// elbm_init without the device-side validation of rho0/u0 (and so without
+// its synchronisation): for callers that validated the fields on the host.
+elbm_status init_sim(const elbm_config* cfg, const double* rho0, const double* u0,
+                     void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out,
+                     bool validate);
+
+// Free a handle whose stream work the caller knows to be complete (no sync).
+void release_sim(elbm_sim* sim) { delete sim; }
+
+// Set the calling thread's error message.
+elbm_status set_error(elbm_status st, const char* msg) { return fail(st, "%s", msg); }
+
+}  // namespace elbm
+
+extern "C" elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* u0,
+                                 void* dev_state, size_t bytes, void* hip_stream,
+                                 elbm_sim** out) {
+  return elbm::init_sim(cfg, rho0, u0, dev_state, bytes, hip_stream, out, true);
+}
+
+elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const double* u0,
+                           void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out,
+                           bool validate) {
   if (!out) return fail(ELBM_EINVAL, "out is NULL");
   *out = nullptr;
   Layout L;
@@ -302,11 +327,12 @@ elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* 
 
   const BoxDesc b = box_of(s);
   unsigned long long nbad = 0;
-  if ((e = hipMemsetAsync(s->counter, 0, sizeof(unsigned long long), s->stream)) != hipSuccess ||
+  if (validate &&
+      ((e = hipMemsetAsync(s->counter, 0, sizeof(unsigned long long), s->stream)) != hipSuccess ||
       (e = launch_validate_init(b, rho0, u0, s->counter, s->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(&nbad, s->counter, sizeof nbad, hipMemcpyDeviceToHost, s->stream)) !=
           hipSuccess ||
-      (e = hipStreamSynchronize(s->stream)) != hipSuccess) {
+      (e = hipStreamSynchronize(s->stream)) != hipSuccess)) {
     delete s;
     return hip_fail(e, "elbm_init validation");
   }
@@ -326,6 +352,8 @@ elbm_status elbm_init(const elbm_config* cfg, const double* rho0, const double* 
   *out = s;
   return ELBM_OK;
 }
+
+extern "C" {
 
 elbm_status elbm_set_populations(elbm_sim* s, const double* f) {
   elbm_status st = check_sim(s);

@@ -27,7 +27,10 @@ STATUS = {0: "ELBM_OK", -1: "ELBM_EINVAL", -2: "ELBM_EDEVICE", -3: "ELBM_ENOMEM"
 EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_populations",
            "elbm_step", "elbm_moments", "elbm_populations", "elbm_gather",
            "elbm_alpha_field", "elbm_stats", "elbm_time", "elbm_destroy",
-           "elbm_last_error", "elbm_step_batch"]
+           "elbm_last_error", "elbm_step_batch", "elbm_server_create", "elbm_server_submit",
+           "elbm_server_poll", "elbm_server_wait", "elbm_server_sim", "elbm_server_release",
+           "elbm_server_get_stats", "elbm_server_destroy"]
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
 class ElbmError(RuntimeError):
@@ -53,6 +56,30 @@ class Stats(C.Structure):
                 ("total_iters", C.c_int64), ("alpha_min", C.c_double),
                 ("alpha_max", C.c_double), ("sum_rho", C.c_double),
                 ("sum_j", C.c_double * 3), ("sum_H", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("hip_stream", C.c_void_p),
+                ("max_active", C.c_int32), ("round_steps", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("cfg", Config), ("rho0", C.c_void_p), ("u0", C.c_void_p),
+                ("nsteps", C.c_int64), ("out_rho", C.c_void_p), ("out_u", C.c_void_p),
+                ("keep_state", C.c_int32), ("reserved", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("reserved", C.c_int32), ("steps_done", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("footprint", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("rounds", C.c_int64), ("launches", C.c_int64), ("site_updates", C.c_int64),
+                ("max_resident", C.c_int64), ("t_first_submit", C.c_double),
+                ("t_last_done", C.c_double)]
 
 
 _lib = None
@@ -84,6 +111,14 @@ def lib():
         L.elbm_last_error.argtypes = []
         L.elbm_last_error.restype = C.c_char_p
         L.elbm_step_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32]
+        L.elbm_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.elbm_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_int64)]
+        L.elbm_server_poll.argtypes = [vp, C.c_int64, C.POINTER(RequestInfo)]
+        L.elbm_server_wait.argtypes = [vp, C.c_int64, C.c_double]
+        L.elbm_server_sim.argtypes = [vp, C.c_int64, C.POINTER(vp)]
+        L.elbm_server_release.argtypes = [vp, C.c_int64]
+        L.elbm_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.elbm_server_destroy.argtypes = [vp]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.elbm_state_bytes.restype = C.c_size_t
@@ -232,3 +267,99 @@ def step_batch(sims, nsteps):
     hs = (C.c_void_p * n)(*[s.handle for s in sims])
     ns = (C.c_int64 * n)(*[int(k) for k in nsteps])
     _check(lib().elbm_step_batch(hs, ns, n))
+
+
+class KeptSimulation(Simulation):
+    """A simulation kept resident by a server (keep_state=1): the handle and
+    its state belong to the server; close() releases them back to the pool."""
+
+    def __init__(self, server: "Server", rid: int, cfg: Config, handle):
+        self.cfg = cfg
+        self.D = cfg.lattice
+        self.Q = 3 ** self.D
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        self.device = server.device
+        self.stream = server.stream
+        self.handle = handle
+        self._server, self._rid = server, rid
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.handle = None
+            if self._server.handle:  # a destroyed server has freed it already
+                _check(lib().elbm_server_release(self._server.handle, self._rid))
+
+
+class Server:
+    """Continuous-batching server over one device memory pool.
+
+    pool_bytes of device memory are allocated here (torch) and handed to the
+    library, which sub-allocates the states of admitted requests.  All server
+    work runs on `stream`."""
+
+    def __init__(self, pool_bytes: int, *, max_active: int = 64, round_steps: int = 50,
+                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+            sc = ServerConfig(C.c_void_p(self.pool.data_ptr()), int(pool_bytes),
+                              C.c_void_p(self.stream.cuda_stream), int(max_active),
+                              int(round_steps))
+            h = C.c_void_p()
+            _check(lib().elbm_server_create(C.byref(sc), C.byref(h)))
+        self.handle = h
+        self._cfgs = {}
+        self._keep = {}
+
+    def submit(self, lattice, nx, ny=1, nz=1, *, rho0, u0, nsteps: int, out_rho=None,
+               out_u=None, keep_state: bool = False, **kw) -> int:
+        """Queue a request; rho0 [N] and u0 [D, N] are host arrays (copied
+        here).  out_rho [N] / out_u [D, N] float64 device tensors, or None."""
+        import numpy as np
+        cfg = make_config(lattice, nx, ny, nz, **kw)
+        r = np.ascontiguousarray(np.asarray(rho0, dtype=np.float64).reshape(-1))
+        u = np.ascontiguousarray(np.asarray(u0, dtype=np.float64).reshape(-1))
+        q = Request(cfg, C.c_void_p(r.ctypes.data), C.c_void_p(u.ctypes.data), int(nsteps),
+                    _ptr(out_rho), _ptr(out_u), 1 if keep_state else 0, 0)
+        rid = C.c_int64()
+        _check(lib().elbm_server_submit(self.handle, C.byref(q), C.byref(rid)))
+        self._cfgs[rid.value] = cfg
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        i = RequestInfo()
+        _check(lib().elbm_server_poll(self.handle, int(rid), C.byref(i)))
+        return dict(state=REQ_STATES[i.state], steps_done=i.steps_done, t_submit=i.t_submit,
+                    t_admit=i.t_admit, t_done=i.t_done, footprint=i.footprint)
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        _check(lib().elbm_server_wait(self.handle, int(rid), float(timeout)))
+
+    def simulation(self, rid: int) -> KeptSimulation:
+        h = C.c_void_p()
+        _check(lib().elbm_server_sim(self.handle, int(rid), C.byref(h)))
+        return KeptSimulation(self, int(rid), self._cfgs[int(rid)], h)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().elbm_server_get_stats(self.handle, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            h, self.handle = self.handle, None
+            _check(lib().elbm_server_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -108,3 +108,28 @@ def random_populations(weights, N: int, eps: float, seed: int, tilt: float = 0.1
     tau = np.linspace(-1.0, 1.0, Q)
     f = w[:, None] * rho[None, :] * (1.0 + e[None, :] * xi) * (1.0 + t[None, :] * tau[:, None])
     return np.ascontiguousarray(f)
+
+
+SERVING_SIZES = (128, 256, 512, 1024, 2048)
+
+
+def serving_stream(n_req: int, rate: float = 20.0, seed: int = 20250101,
+                   sizes=SERVING_SIZES, re_range=(1e3, 1e5), steps_range=(1000, 20000),
+                   storages=("f32", "f16dev")):
+    """Seeded request stream of D2Q9 doubly periodic shear-layer solves:
+    Poisson arrivals at `rate` per second (exponential gaps), box edge
+    uniform over `sizes`, Reynolds number log-uniform over `re_range`, step
+    count uniform over the integers of `steps_range`, storage uniform over
+    `storages`.  Each request gets beta from nu = 0.04 n / Re (shear_beta)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n_req):
+        t += rng.exponential(1.0 / rate)
+        n = int(sizes[rng.integers(0, len(sizes))])
+        re = float(np.exp(rng.uniform(math.log(re_range[0]), math.log(re_range[1]))))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        storage = storages[int(rng.integers(0, len(storages)))]
+        out.append(dict(k=k, arrival=t, n=n, re=re, steps=steps, storage=storage,
+                        beta=shear_beta(n, re=re)))
+    return out

@@ -37,13 +37,20 @@ def test_struct_layout_matches_header(tmp_path):
 int main(void) {{
   printf("%zu %zu %zu %zu %zu\\n", sizeof(elbm_config), offsetof(elbm_config, beta),
          offsetof(elbm_config, rho_ref), offsetof(elbm_config, diag), sizeof(elbm_stats_t));
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(elbm_server_config), sizeof(elbm_request),
+         offsetof(elbm_request, nsteps), offsetof(elbm_request, keep_state),
+         sizeof(elbm_request_info), offsetof(elbm_request_info, footprint),
+         sizeof(elbm_server_stats));
   return 0;
 }}''')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
     got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     want = [C.sizeof(elbm.Config), elbm.Config.beta.offset, elbm.Config.rho_ref.offset,
-            elbm.Config.diag.offset, C.sizeof(elbm.Stats)]
+            elbm.Config.diag.offset, C.sizeof(elbm.Stats),
+            C.sizeof(elbm.ServerConfig), C.sizeof(elbm.Request), elbm.Request.nsteps.offset,
+            elbm.Request.keep_state.offset, C.sizeof(elbm.RequestInfo),
+            elbm.RequestInfo.footprint.offset, C.sizeof(elbm.ServerStats)]
     assert [int(v) for v in got] == want
 
 
@@ -111,3 +118,24 @@ def test_batch_argument_errors():
     assert L.elbm_step_batch(None, None, 0) == 0
     assert L.elbm_step_batch(None, None, -1) == -1
     assert L.elbm_step_batch(None, None, 2) == -1
+
+
+def test_server_argument_errors_before_device_work():
+    L = elbm.lib()
+    h = C.c_void_p()
+    sc = elbm.ServerConfig(None, 1 << 20, None, 4, 10)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    assert b"pool" in L.elbm_last_error()
+    sc = elbm.ServerConfig(C.c_void_p(4096 + 8), 1 << 20, None, 4, 10)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    assert b"aligned" in L.elbm_last_error()
+    sc = elbm.ServerConfig(C.c_void_p(4096), 1 << 20, None, 0, 10)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    sc = elbm.ServerConfig(C.c_void_p(4096), 1 << 20, None, 4, 0)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    assert L.elbm_server_create(None, C.byref(h)) == -1
+    assert L.elbm_server_submit(None, None, None) == -1
+    assert L.elbm_server_poll(None, 1, None) == -1
+    assert L.elbm_server_wait(None, 1, 0.0) == -1
+    assert L.elbm_server_release(None, 1) == -1
+    assert L.elbm_server_destroy(None) == 0

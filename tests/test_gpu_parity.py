@@ -289,3 +289,23 @@ def test_full_size_d3q27_512_sampled(gpu, orc):
         assert np.all(np.abs(post[:, k] - ft) <= 2.0 ** -24 * np.abs(ft) * 1.01), sites[k]
     sim.close()
     torch.cuda.empty_cache()
+
+
+def test_shock_tube_d1q3_alpha_field(gpu, orc):
+    """D1Q3 shock tube run to t = 500 on the GPU (FP64 storage): populations
+    and the alpha field of the next step match the oracle."""
+    n, split, T = 800, 400, 500
+    x = np.arange(n)
+    rho = np.where(x <= split, 1.5, 0.75)
+    u = np.zeros((1, n))
+    beta = (1.0 / 3.0) / (2.0 * 1e-5 + 1.0 / 3.0)
+    sim = _sim(gpu, 1, (n, 1, 1), rho=rho, u=u, storage="f64", beta=beta, diag=gpu.DIAG_ALPHA)
+    sim.step(T + 1)
+    ag = sim.alpha_field().cpu().numpy()
+    cfg = _ocfg(orc, 1, (n, 1, 1), beta=beta)
+    fo, _, _ = orc.run(cfg, orc.init(cfg, rho, u), T)
+    _, ao, _ = orc.step(cfg, fo, want_alpha=True)
+    assert np.max(np.abs(ag - ao)) <= 1e-9
+    dev = np.abs(2.0 - ag[split + 1:]).max() / 2.0 * 100.0
+    assert abs(dev - 3.96) < 0.5
+    sim.close()

@@ -1,0 +1,199 @@
+"""Serving (elbm_server_*): each request's result is the same in the mix as
+alone (bitwise: the batched step computes every site exactly as the single
+step does), admission under a pool that holds one request at a time, kept
+states, and isolation of a request that goes non-finite."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_00866_amd import serving
+from paper_1904_00866_amd import workloads as Wk
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields(D, shape, seed):
+    N = int(np.prod(shape))
+    if D == 2 and shape[0] == shape[1]:
+        rho, u = Wk.shear_layer(shape[0])
+        return rho.reshape(-1), u.reshape(2, -1)
+    rho, u = Wk.random_velocity_field(D, N, 0.05, seed=seed)
+    return rho, u
+
+
+def _alone(gpu, D, shape, rho, u, steps, **kw):
+    with gpu.Simulation(D, *shape, rho0=rho, u0=u, **kw) as s:
+        s.step(steps)
+        r, v = s.moments()
+        torch.cuda.synchronize()
+        return r.cpu().numpy(), v.cpu().numpy(), s.populations().cpu().numpy()
+
+
+MIX = [  # (D, shape, steps, kwargs)
+    (2, (64, 64, 1), 120, dict(storage="f32", beta=0.99)),
+    (2, (37, 23, 1), 75, dict(storage="f16dev", beta=0.97)),
+    (2, (128, 128, 1), 200, dict(storage="f32", beta=0.995)),
+    (2, (48, 40, 1), 0, dict(storage="f32", beta=0.99)),
+    (3, (16, 12, 9), 60, dict(storage="f32", beta=0.98)),
+    (2, (64, 64, 1), 90, dict(storage="f32", beta=0.99, mode="bgk")),
+    (2, (96, 96, 1), 150, dict(storage="f16dev", beta=0.99)),
+    (2, (33, 65, 1), 41, dict(storage="f64", beta=0.9)),
+    (2, (256, 256, 1), 64, dict(storage="f32", beta=0.999)),
+    (3, (20, 20, 20), 30, dict(storage="f16dev", beta=0.99)),
+    (2, (64, 64, 1), 120, dict(storage="f32", beta=0.99)),
+    (2, (50, 50, 1), 333, dict(storage="f32", beta=0.96, mode="secant")),
+]
+
+
+def test_server_mix_equals_alone(gpu):
+    """Twelve requests of mixed lattices, sizes, storages, modes and step
+    counts, arriving while earlier ones run (5 slots, 37-step rounds): the
+    final rho, u of each equal those of the same simulation advanced alone."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.Stream()
+    fields = [_fields(D, shp, 100 + k) for k, (D, shp, _, _) in enumerate(MIX)]
+    outs, ids = [], []
+    with gpu.Server(256 << 20, max_active=5, round_steps=37, stream=stream) as srv:
+        for k, ((D, shp, steps, kw), (rho, u)) in enumerate(zip(MIX, fields)):
+            N = int(np.prod(shp))
+            with torch.cuda.stream(stream):
+                o = (torch.empty(N, dtype=torch.float64, device=dev),
+                     torch.empty(D, N, dtype=torch.float64, device=dev))
+            outs.append(o)
+            ids.append(srv.submit(D, *shp, rho0=rho, u0=u, nsteps=steps, out_rho=o[0],
+                                  out_u=o[1], **kw))
+            if k % 3 == 2:
+                time.sleep(0.005)
+        for i in ids:
+            srv.wait(i, 60.0)
+        st = srv.stats()
+        infos = [srv.poll(i) for i in ids]
+    torch.cuda.synchronize()
+    assert st["completed"] == len(MIX) and st["failed"] == 0
+    assert 1 < st["max_resident"] <= 5
+    assert st["site_updates"] == sum(int(np.prod(s)) * n for _, s, n, _ in MIX)
+    for k, ((D, shp, steps, kw), (rho, u), inf) in enumerate(zip(MIX, fields, infos)):
+        assert inf["state"] == "done" and inf["steps_done"] == steps
+        assert inf["t_submit"] <= inf["t_admit"] <= inf["t_done"]
+        r0, u0, _ = _alone(gpu, D, shp, rho, u, steps, **kw)
+        assert np.array_equal(outs[k][0].cpu().numpy(), r0), k
+        assert np.array_equal(outs[k][1].cpu().numpy(), u0), k
+
+
+def test_server_admission_small_pool(gpu):
+    """A pool that fits one request at a time: requests run one after
+    another in arrival order; one that can never fit is rejected."""
+    reqs = [dict(k=k, n=n, steps=s, storage="f32", beta=0.99, arrival=0.0)
+            for k, (n, s) in enumerate([(128, 40), (96, 30), (128, 20), (64, 50)])]
+    pool = max(serving.footprint(r) for r in reqs) + 4096
+    stream = torch.cuda.Stream()
+    with gpu.Server(pool, max_active=8, round_steps=16, stream=stream) as srv:
+        big = Wk.shear_layer(512)
+        with pytest.raises(gpu.ElbmError) as e:
+            srv.submit("d2q9", 512, 512, 1, rho0=big[0], u0=big[1], nsteps=1)
+        assert e.value.status == -3
+        ids = []
+        for r in reqs:
+            rho, u = Wk.shear_layer(r["n"])
+            ids.append(srv.submit("d2q9", r["n"], r["n"], 1, rho0=rho, u0=u,
+                                  nsteps=r["steps"], beta=r["beta"]))
+        for i in ids:
+            srv.wait(i, 60.0)
+        infos = [srv.poll(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == 4 and st["max_resident"] == 1
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_admit"] >= a["t_done"]
+    assert all(inf["footprint"] == serving.footprint(r) for inf, r in zip(infos, reqs))
+
+
+def test_server_keep_state_and_release(gpu):
+    """A kept simulation continues outside the server exactly as an
+    uninterrupted run; releasing it frees its pool block for the next
+    request."""
+    n, s1, s2 = 64, 70, 30
+    rho, u = Wk.shear_layer(n)
+    req = dict(n=n, storage="f32", beta=0.99)
+    pool = serving.footprint(req) + 4096
+    stream = torch.cuda.Stream()
+    _, _, ref = _alone(gpu, 2, (n, n, 1), rho, u, s1 + s2, storage="f32", beta=0.99)
+    with gpu.Server(pool, max_active=4, round_steps=25, stream=stream) as srv:
+        i = srv.submit("d2q9", n, n, 1, rho0=rho, u0=u, nsteps=s1, keep_state=True,
+                       storage="f32", beta=0.99)
+        srv.wait(i, 60.0)
+        sim = srv.simulation(i)
+        assert sim.t == s1
+        with torch.cuda.stream(stream):
+            sim.step(s2)
+            f = sim.populations()
+        stream.synchronize()
+        assert np.array_equal(f.cpu().numpy(), ref)
+        j = srv.submit("d2q9", n, n, 1, rho0=rho, u0=u, nsteps=5, storage="f32", beta=0.99)
+        time.sleep(0.2)
+        assert srv.poll(j)["state"] == "queued"  # the kept state holds the pool
+        sim.close()  # elbm_server_release
+        srv.wait(j, 60.0)
+        assert srv.poll(j)["state"] == "done"
+        with pytest.raises(gpu.ElbmError):
+            srv.simulation(j)  # not a keep_state request
+
+
+def test_server_isolates_a_diverging_request(gpu):
+    """An LBGK request that diverges (a sharp shear layer at nu ~ 1e-6) in
+    the same batched launches as two stable LBGK requests: the stable ones
+    still equal their alone runs.  Invalid requests are rejected at
+    submission without disturbing the others."""
+    n = 48
+    bad = Wk.shear_layer(n, u0=0.3, kappa=200.0)
+    good = [Wk.shear_layer(64), Wk.shear_layer(n)]
+    dev = torch.device("cuda")
+    stream = torch.cuda.Stream()
+    outs = []
+    with gpu.Server(64 << 20, max_active=4, round_steps=50, stream=stream) as srv:
+        with torch.cuda.stream(stream):
+            for m in (64, n, n):
+                outs.append((torch.empty(m * m, dtype=torch.float64, device=dev),
+                             torch.empty(2, m * m, dtype=torch.float64, device=dev)))
+        ids = [srv.submit("d2q9", 64, 64, 1, rho0=good[0][0], u0=good[0][1], nsteps=400,
+                          out_rho=outs[0][0], out_u=outs[0][1], mode="bgk", beta=0.95),
+               srv.submit("d2q9", n, n, 1, rho0=bad[0], u0=bad[1], nsteps=400,
+                          out_rho=outs[2][0], out_u=outs[2][1], mode="bgk", beta=0.99999),
+               srv.submit("d2q9", n, n, 1, rho0=good[1][0], u0=good[1][1], nsteps=300,
+                          out_rho=outs[1][0], out_u=outs[1][1], mode="bgk", beta=0.95)]
+        rho_bad = np.ones(n * n)
+        rho_bad[7] = np.nan
+        for r, u in [(rho_bad, good[1][1]), (-good[1][0], good[1][1]),
+                     (good[1][0], good[1][1] * 30.0)]:
+            with pytest.raises(gpu.ElbmError) as e:
+                srv.submit("d2q9", n, n, 1, rho0=r, u0=u, nsteps=10, mode="bgk")
+            assert e.value.status == -1
+        for i in ids:
+            srv.wait(i, 60.0)
+        st = srv.stats()
+    torch.cuda.synchronize()
+    assert st["completed"] == 3 and st["failed"] == 0 and st["submitted"] == 3
+    for (m, steps, (rho, u)), o in zip([(64, 400, good[0]), (n, 300, good[1])], outs):
+        r0, u0, _ = _alone(gpu, 2, (m, m, 1), rho, u, steps, mode="bgk", beta=0.95,
+                           storage="f32")
+        assert np.array_equal(o[0].cpu().numpy(), r0)
+        assert np.array_equal(o[1].cpu().numpy(), u0)
+    ub = outs[2][1].cpu().numpy()
+    assert not np.all(np.isfinite(ub)) or np.abs(ub).max() > 1.0
+
+
+def test_serving_stream_small(gpu):
+    """A short seeded stream through the Python driver: every request
+    completes, latencies are positive, and two sampled requests equal their
+    alone runs."""
+    reqs = Wk.serving_stream(10, rate=50.0, seed=7, sizes=(64, 128, 256),
+                             steps_range=(50, 400))
+    res = serving.run_stream(reqs, max_active=4, round_steps=40, keep=(0, 5))
+    assert res["completed"] == 10 and res["failed"] == 0
+    assert 0 < res["p50_s"] <= res["p99_s"]
+    for k in (0, 5):
+        r0, u0 = serving.run_alone(reqs[k])
+        torch.cuda.synchronize()
+        assert torch.equal(res["outputs"][k][0], r0)
+        assert torch.equal(res["outputs"][k][1], u0)

@@ -441,3 +441,25 @@ def test_accept2_proportion_on_double_shear(orc):
     assert abs(late.mean() - target) < 0.1
     assert np.mean(np.abs(late - target) < 0.15) > 0.8
     assert all(d["n_negative"] == 0 for _, d in diags)
+
+
+def test_shock_tube_alpha_deviation(orc):
+    """Shock tube (Fig. 2): rho = 1.5 on 0 <= x <= 400, 0.75 on 400 < x <= 800,
+    u = 0, nu = 1e-5, D1Q3.  At t = 500 the largest deviation of alpha from 2
+    at the compressive front moving right from the split is printed as 3.96 %
+    (periodic box of 800 sites; the front's region is 400 < x < 800, clear of
+    the second front that the periodic wrap launches from x = 800)."""
+    g = GOLD["shock_tube_alpha_deviation_percent"]
+    st = g["setup"]
+    n, split = st["length"], st["split"]
+    x = np.arange(n)
+    rho = np.where(x <= split, st["rho_left"], st["rho_right"])
+    beta = (1.0 / 3.0) / (2.0 * st["nu"] + 1.0 / 3.0)
+    cfg = orc.Config(D=1, nx=n, beta=beta)
+    f, _, _ = orc.run(cfg, orc.init(cfg, rho, np.zeros((1, n))), st["t"])
+    _, alpha, d = orc.step(cfg, f, want_alpha=True, want_diag=True)
+    dev = np.abs(2.0 - alpha) / 2.0 * 100.0
+    front = dev[split + 1:]
+    assert abs(front.max() - g["value"]) < 0.5
+    assert 600 < split + 1 + int(front.argmax()) < 780  # the front, not the split
+    assert np.all(alpha <= 2.0) and d["n_negative"] == 0
