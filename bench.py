@@ -36,13 +36,20 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+# Sources that make up the step kernels (host runtime and server excluded).
+STEP_KERNEL_SOURCES = ("elbm_internal.hpp", "elbm_site.hpp", "elbm_step_impl.hpp",
+                       "elbm_step_d1.hip", "elbm_step_d2.hip", "elbm_step_d3.hip")
+
+
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
+    """Hash of the step kernels' sources and compile flags: a stored counter
+    measurement is used only while this hash is unchanged."""
+    from paper_1904_00866_amd import build as B
+    h = hashlib.sha256(" ".join(f for f in B.flags() if not f.startswith("-I")).encode())
     csrc = os.path.join(ROOT, "paper_1904_00866_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -111,6 +118,67 @@ def cpu_baseline(n_full, beta, budget_s=10.0):
                       f"({platform.processor() or platform.machine()})"}
 
 
+def _serving_summary(res, rate):
+    return {"n_req": res["n_req"], "rate_per_s": rate, "completed": res["completed"],
+            "failed": res["failed"], "p50_s": round(res["p50_s"], 3),
+            "p99_s": round(res["p99_s"], 3), "mean_s": round(res["mean_s"], 3),
+            "queue_wait_p50_s": round(res["queue_p50_s"], 3),
+            "queue_wait_p99_s": round(res["queue_p99_s"], 3),
+            "aggregate_mlups": round(res["mlups"], 1), "span_s": round(res["span_s"], 2),
+            "site_updates": res["site_updates"], "rounds": res["rounds"],
+            "launches": res["launches"], "max_resident": res["max_resident"],
+            "submit_lag_max_s": round(res["submit_lag_max_s"], 4)}
+
+
+def serving_block(args) -> dict:
+    """Two seeded Poisson streams of D2Q9 shear-layer requests through the
+    continuous-batching server: the overloaded stream (arrivals faster than
+    the GPU can serve) and one below capacity; four sampled requests rerun
+    alone and compared with their in-mix results."""
+    import numpy as np
+    import torch
+
+    from paper_1904_00866_amd import serving
+    from paper_1904_00866_amd import workloads as Wk
+
+    max_active, round_steps = 64, 50
+    reqs = Wk.serving_stream(args.serving_requests, rate=args.serving_rate)
+    rng = np.random.default_rng(1)
+    cand = [r["k"] for r in reqs if r["n"] <= 1024]
+    sample = sorted(int(k) for k in rng.choice(cand, size=min(4, len(cand)), replace=False))
+    log(f"serving: {len(reqs)} requests at {args.serving_rate}/s")
+    res = serving.run_stream(reqs, max_active=max_active, round_steps=round_steps,
+                             keep=sample, log=log)
+    log(f"serving: p50 {res['p50_s']:.2f} s, p99 {res['p99_s']:.2f} s, "
+        f"{res['mlups']:.0f} MLUPS")
+    diff = 0.0
+    for k in sample:
+        r0, u0 = serving.run_alone(reqs[k])
+        o = res["outputs"][k]
+        diff = max(diff, (o[0] - r0).abs().max().item(), (o[1] - u0).abs().max().item())
+    del res["outputs"]
+    torch.cuda.empty_cache()
+    out = {"workload": "D2Q9 doubly periodic shear layers, u0=0.04, kappa=80, delta=0.05; "
+                       "edge uniform in {128,256,512,1024,2048}, Re log-uniform [1e3,1e5], "
+                       "steps uniform [1000,20000], storage uniform {f32,f16dev}, "
+                       "closed-form alpha, nu=0.04 n/Re; seeded Poisson arrivals",
+           "seed": 20250101, "max_active": max_active, "round_steps": round_steps,
+           "pool_bytes": res["pool_bytes"],
+           "stream": _serving_summary(res, args.serving_rate),
+           "alone_vs_mix": {"requests": sample, "max_abs_diff_rho_u": diff}}
+    if args.serving_steady_requests > 0:
+        reqs2 = Wk.serving_stream(args.serving_steady_requests, rate=args.serving_steady_rate,
+                                  seed=20250102)
+        log(f"serving: {len(reqs2)} requests at {args.serving_steady_rate}/s")
+        res2 = serving.run_stream(reqs2, max_active=max_active, round_steps=round_steps,
+                                  log=log)
+        log(f"serving: p50 {res2['p50_s']:.2f} s, p99 {res2['p99_s']:.2f} s")
+        del res2["outputs"]
+        out["steady_stream"] = dict(_serving_summary(res2, args.serving_steady_rate),
+                                    seed=20250102)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +191,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None, choices=["closed", "newton", "bisect", "bgk"],
                     help="time one alpha mode only (profiling runs)")
+    ap.add_argument("--serving-requests", type=int, default=64,
+                    help="requests of the Poisson serving stream (0: skip serving)")
+    ap.add_argument("--serving-rate", type=float, default=20.0)
+    ap.add_argument("--serving-steady-requests", type=int, default=24)
+    ap.add_argument("--serving-steady-rate", type=float, default=3.0,
+                    help="arrival rate of the second stream, below capacity")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (a known-size kernel "
                          "that calibrates hardware byte counters in profiling runs)")
@@ -222,6 +296,8 @@ def main() -> int:
             cmp["bgk_mlups"] = round(N / results["bgk"]["ms"] / 1e3, 1)
             cmp["closed_over_bgk_time"] = round(ms / results["bgk"]["ms"], 3)
         out["comparison"] = cmp
+    if args.serving_requests > 0 and not args.only:
+        out["serving"] = serving_block(args)
     if not args.no_cpu_baseline and not args.only:
         log("CPU oracle baseline (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(n, beta)

@@ -209,9 +209,17 @@ hipEvent_t take_event(elbm_server* s) {
   return e;
 }
 
-// Admission, first come first served (caller holds the lock).
-void admit(elbm_server* s) {
-  while (!s->broken && !s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
+// Admission, first come first served.  Pool blocks are taken with the lock
+// held; the copies and launches run with it released (a launch can block
+// while the device queue is full, and submitters must not wait on that).
+void admit(elbm_server* s, std::unique_lock<std::mutex>& lk) {
+  struct Adm {
+    Req* r;
+    size_t soff;
+  };
+  std::vector<Adm> take;
+  size_t slots = s->active.size();
+  while (!s->broken && !s->queue.empty() && (int)slots < s->cfg.max_active) {
     Req* r = s->queue.front();
     size_t off = 0, soff = 0;
     if (!s->pool->alloc(r->state_bytes, &off)) break;
@@ -220,89 +228,124 @@ void admit(elbm_server* s) {
       break;
     }
     s->queue.pop_front();
-    double* stage = reinterpret_cast<double*>(s->base + soff);
+    r->off = off;
+    take.push_back({r, soff});
+    ++slots;
+  }
+  if (take.empty()) return;
+  std::vector<elbm_status> st(take.size(), ELBM_EDEVICE);
+  bool any_failed = false;
+  lk.unlock();
+  for (size_t k = 0; k < take.size(); ++k) {
+    Req* r = take[k].r;
+    double* stage = reinterpret_cast<double*>(s->base + take[k].soff);
     const size_t nbytes = size_t(r->N) * (1 + r->cfg.lattice) * sizeof(double);
-    hipError_t e = hipMemcpyAsync(stage, r->host.p, nbytes, hipMemcpyHostToDevice, s->stream);
-    elbm_status st = ELBM_EDEVICE;
-    if (e == hipSuccess)
-      st = elbm::init_sim(&r->cfg, stage, stage + r->N, s->base + off, r->state_bytes,
-                          s->stream, &r->sim, false);
-    if (st != ELBM_OK) {
-      // nothing of this request may still be in use on the stream
-      (void)hipStreamSynchronize(s->stream);
-      s->pool->release(off, r->state_bytes);
-      s->pool->release(soff, r->stage_bytes);
+    if (hipMemcpyAsync(stage, r->host.p, nbytes, hipMemcpyHostToDevice, s->stream) == hipSuccess)
+      st[k] = elbm::init_sim(&r->cfg, stage, stage + r->N, s->base + r->off, r->state_bytes,
+                             s->stream, &r->sim, false);
+    any_failed |= st[k] != ELBM_OK;
+  }
+  // nothing of a failed admission may still be in use on the stream
+  if (any_failed) (void)hipStreamSynchronize(s->stream);
+  lk.lock();
+  const double t = now_s() - s->t0;
+  for (size_t k = 0; k < take.size(); ++k) {
+    Req* r = take[k].r;
+    if (st[k] != ELBM_OK) {
+      s->pool->release(r->off, r->state_bytes);
+      s->pool->release(take[k].soff, r->stage_bytes);
       recycle_pinned(s, r->host);
       r->host = Pinned{};
       fail_req(s, r);
       continue;
     }
-    r->off = off;
     r->state = ELBM_REQ_RUNNING;
-    r->t_admit = now_s() - s->t0;
+    r->t_admit = t;
     s->active.push_back(r);
-    s->stats.max_resident = std::max<int64_t>(s->stats.max_resident, (int64_t)s->active.size());
-    s->pending.staging.push_back({soff, r->stage_bytes});
+    s->pending.staging.push_back({take[k].soff, r->stage_bytes});
     s->pending.pinned.push_back(r->host);
     r->host = Pinned{};
   }
+  s->stats.max_resident = std::max<int64_t>(s->stats.max_resident, (int64_t)s->active.size());
 }
 
-// Enqueue one round over the resident simulations (caller holds the lock).
-bool launch_round(elbm_server* s) {
+// Enqueue one round over the resident simulations.  Only this thread touches
+// the resident simulations, so the launches run with the lock released.
+void launch_round(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   Round rd = std::move(s->pending);
   s->pending = Round{};
   std::vector<Req*> act = s->active;
-  std::stable_sort(act.begin(), act.end(), group_less);
+  std::vector<int64_t> todo(act.size());
+  for (size_t k = 0; k < act.size(); ++k)
+    todo[k] = std::min<int64_t>(act[k]->nsteps - act[k]->done, s->cfg.round_steps);
+  lk.unlock();
+  std::vector<size_t> order(act.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t a, size_t b) { return group_less(act[a], act[b]); });
+  std::string err;
+  int64_t launches = 0;
   std::vector<elbm_sim*> sims;
   std::vector<int64_t> steps;
-  for (size_t g0 = 0, g1; g0 < act.size(); g0 = g1) {
+  for (size_t g0 = 0, g1; g0 < order.size() && err.empty(); g0 = g1) {
     g1 = g0 + 1;
-    while (g1 < act.size() && same_group(act[g0], act[g1])) ++g1;
+    while (g1 < order.size() && same_group(act[order[g0]], act[order[g1]])) ++g1;
     sims.clear();
     steps.clear();
     for (size_t k = g0; k < g1; ++k) {
-      Req* r = act[k];
-      const int64_t n = std::min<int64_t>(r->nsteps - r->done, s->cfg.round_steps);
-      sims.push_back(r->sim);
-      steps.push_back(n);
-      rd.updates += n * r->N;
+      sims.push_back(act[order[k]]->sim);
+      steps.push_back(todo[order[k]]);
+      rd.updates += todo[order[k]] * act[order[k]]->N;
     }
     if (elbm_step_batch(sims.data(), steps.data(), (int32_t)sims.size()) != ELBM_OK) {
-      mark_broken(s, std::string("step launch: ") + elbm_last_error());
-      s->pending = std::move(rd);
-      return false;
+      err = std::string("step launch: ") + elbm_last_error();
+      break;
     }
-    // one launch per step and per kMaxBatch residents still stepping
+    // one launch per step and per kMaxBatch simulations still stepping
     std::sort(steps.begin(), steps.end());
     int64_t prev = 0;
     for (size_t k = 0; k < steps.size(); ++k) {
       const int64_t left = int64_t(steps.size() - k);
-      s->stats.launches += (steps[k] - prev) * ((left + elbm::kMaxBatch - 1) / elbm::kMaxBatch);
+      launches += (steps[k] - prev) * ((left + elbm::kMaxBatch - 1) / elbm::kMaxBatch);
       prev = steps[k];
     }
   }
-  std::vector<Req*> still;
-  for (Req* r : s->active) {
-    r->done += std::min<int64_t>(r->nsteps - r->done, s->cfg.round_steps);
-    if (r->done >= r->nsteps) {
-      if (r->out_rho && elbm_moments(r->sim, r->out_rho, r->out_u) != ELBM_OK)
-        mark_broken(s, std::string("moments: ") + elbm_last_error());
-      rd.finished.push_back(r);
-    } else {
-      still.push_back(r);
+  std::vector<char> fin(act.size(), 0);
+  for (size_t k = 0; k < act.size() && err.empty(); ++k) {
+    Req* r = act[k];
+    if (r->done + todo[k] < r->nsteps) continue;
+    fin[k] = 1;
+    if (r->out_rho && elbm_moments(r->sim, r->out_rho, r->out_u) != ELBM_OK)
+      err = std::string("moments: ") + elbm_last_error();
+  }
+  hipEvent_t ev = nullptr;
+  if (err.empty()) {
+    ev = take_event(s);
+    if (!ev || hipEventRecord(ev, s->stream) != hipSuccess) {
+      err = "hipEventRecord failed";
+      if (ev) s->spare_events.push_back(ev);
+      ev = nullptr;
     }
   }
-  s->active.swap(still);
-  rd.ev = take_event(s);
-  if (!rd.ev || hipEventRecord(rd.ev, s->stream) != hipSuccess) {
-    mark_broken(s, "hipEventRecord failed");
-    if (rd.ev) s->spare_events.push_back(rd.ev);
-    rd.ev = nullptr;
-  }
+  lk.lock();
+  s->stats.launches += launches;
   s->stats.rounds++;
+  if (!err.empty()) {
+    mark_broken(s, err);
+    s->pending = std::move(rd);  // freed once the stream has been drained
+    return;
+  }
+  std::vector<Req*> still;
+  for (size_t k = 0; k < act.size(); ++k) {
+    act[k]->done += todo[k];
+    if (fin[k])
+      rd.finished.push_back(act[k]);
+    else
+      still.push_back(act[k]);
+  }
+  s->active.swap(still);
+  rd.ev = ev;
   s->rounds.push_back(std::move(rd));
-  return !s->broken;
 }
 
 // Retire the oldest round, waiting for the GPU with the lock released.
@@ -350,6 +393,14 @@ void worker_main(elbm_server* s) {
     if (s->broken) {
       // after a device error the stream is not trusted: fail what is left
       while (!s->rounds.empty()) retire_oldest(s, lk);
+      if (!s->pending.staging.empty() || !s->pending.pinned.empty()) {
+        lk.unlock();
+        (void)hipStreamSynchronize(s->stream);
+        lk.lock();
+        for (auto& b : s->pending.staging) s->pool->release(b.first, b.second);
+        for (auto& p : s->pending.pinned) recycle_pinned(s, p);
+        s->pending = Round{};
+      }
       for (Req* r : s->active) {
         elbm::release_sim(r->sim);
         r->sim = nullptr;
@@ -365,9 +416,10 @@ void worker_main(elbm_server* s) {
       seen = s->kick;
       continue;
     }
-    admit(s);
+    admit(s, lk);
+    if (s->broken) continue;
     if (!s->active.empty()) {
-      launch_round(s);
+      launch_round(s, lk);
       continue;
     }
     if (!s->rounds.empty()) {
