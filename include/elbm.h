@@ -76,7 +76,8 @@ enum { ELBM_D1Q3 = 1, ELBM_D2Q9 = 2, ELBM_D3Q27 = 3 };
 
 enum {
   ELBM_ALPHA_CLOSED = 0, /* Eq. (8), acceptance test, Eq. (9)            */
-  ELBM_ALPHA_NEWTON = 1, /* bracketed Newton root of Eq. (4)             */
+  ELBM_ALPHA_NEWTON = 1, /* bracketed Newton root of Eq. (4), from
+                            alpha_*, stop at a step below 1e-13 alpha     */
   ELBM_ALPHA_BISECT = 2, /* bisection root of Eq. (4), window root_tol   */
   ELBM_ALPHA_BGK = 3,    /* alpha = 2 with the polynomial equilibrium    */
   ELBM_ALPHA_SECANT = 4  /* modified secant, secant_iters iterations     */

@@ -221,7 +221,9 @@ static double solve_bisect(const lat_t *L, const double *feq, const double *x,
 /* Bracketed Newton iteration for the root of Eq. (4) on [1, alpha_max],
  * started at alpha_* (at the bracket midpoint when alpha_* = alpha_max, where
  * G' is unbounded).  A step leaving the bracket is replaced by bisection.
- * Stops when the step is below 1e-15 alpha. */
+ * Stops when the step is below 1e-13 alpha: the FP64 rounding of G near its
+ * root already moves alpha by about that much, so smaller steps only follow
+ * rounding noise until the bracket collapses. */
 static double solve_newton(const lat_t *L, const double *feq, const double *x,
                            double amax, double astar, int maxit, int *iters) {
   double lo = 1.0, hi = amax;
@@ -236,7 +238,7 @@ static double solve_newton(const lat_t *L, const double *feq, const double *x,
     else lo = a;
     double an = a - g / dG_of(L, feq, x, a);
     if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
-    if (fabs(an - a) <= 1e-15 * a) return an;
+    if (fabs(an - a) <= 1e-13 * a) return an;
     a = an;
   }
   return a;

@@ -469,7 +469,9 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
           else lo = a;
           R an = a - gv / dS;
           if (!(an > lo && an < hi)) an = R(0.5) * (lo + hi);
-          if (fabs(an - a) <= R(1e-15) * a) {
+          // stop at a step below 1e-13 alpha (rounding of G near the root
+          // moves alpha by about that much)
+          if (fabs(an - a) <= R(1e-13) * a) {
             a = an;
             break;
           }
