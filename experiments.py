@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Measurements of the ELBM hot path beyond the headline benchmark, on one
+MI355X, through the C ABI only (the FP64 GPU path is the reference where one
+is needed; its parity with the CPU oracle is established by the GPU tests).
+
+    python experiments.py w1     D2Q9 64^2 Taylor-Green, FP64, 1000 steps, every
+                                 alpha mode: us/step, decay rate vs Eq. (2), drift
+    python experiments.py w2     D2Q9 1024^2 shear layer, FP32, 20000 steps:
+                                 fraction of sites with alpha < 2, alpha range,
+                                 alpha vs vorticity, MLUPS
+    python experiments.py e2     D2Q9 128^2 shear layer, nu = 1e-5, 3200 steps:
+                                 proportion of sites accepting alpha = 2
+    python experiments.py w4     D3Q27 256^3 Taylor-Green, 2000 steps, storage
+                                 FP64 / FP32 / FP32-dev / FP16-dev under both
+                                 precision policies: velocity and kinetic-energy
+                                 error vs FP64, per-site H increases
+Each prints one JSON object per experiment on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from paper_1904_00866_amd import elbm
+from paper_1904_00866_amd import workloads as Wk
+
+
+def log(msg):
+    print(f"[exp {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _kinetic(rho, u):
+    return 0.5 * float((rho * (u * u).sum(0)).sum())
+
+
+def _timed_steps(sim, n):
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(sim.stream):
+        ev0.record(sim.stream)
+        sim.step(n)
+        ev1.record(sim.stream)
+    ev1.synchronize()
+    return ev0.elapsed_time(ev1) / n
+
+
+# --------------------------------------------------------------------- W1 --
+def w1():
+    n, T, beta = 64, 1000, 0.95
+    rho, u = Wk.taylor_green_2d(n)
+    nu = (1.0 / beta - 1.0) / 6.0
+    k2 = 2.0 * (2.0 * math.pi / n) ** 2
+    out = {"experiment": "w1", "workload": "D2Q9 Taylor-Green 64^2, u0 = 0.05, beta = 0.95, "
+           "FP64 storage, 1000 steps", "nu_eq2": nu, "modes": {}}
+    for mode in ("closed", "secant", "newton", "bisect", "bgk"):
+        with elbm.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f64", beta=beta,
+                             mode=mode, diag=elbm.DIAG_COUNTS | elbm.DIAG_SUMS) as sim:
+            ts, kes, m0 = [], [], None
+            ms_total = 0.0
+            for t in range(0, T + 1, 100):
+                if t:
+                    ms_total += _timed_steps(sim, 100) * 100
+                r, v = sim.moments()
+                torch.cuda.synchronize()
+                ts.append(t)
+                kes.append(_kinetic(r, v))
+                if m0 is None:
+                    m0 = float(r.sum())
+                mass = float(r.sum())
+            st = sim.stats()
+        slope = np.polyfit(ts, np.log(kes), 1)[0]
+        nu_fit = -slope / (2.0 * k2)
+        out["modes"][mode] = {"us_per_step": round(ms_total / T * 1e3, 2),
+                              "nu_fit": nu_fit, "nu_rel_err": (nu_fit - nu) / nu,
+                              "ke_ratio_1000": kes[-1] / kes[0],
+                              "mass_drift_rel": (mass - m0) / m0,
+                              "iters_per_site_last_step": st["total_iters"] / (n * n)}
+        log(f"w1 {mode}: {out['modes'][mode]}")
+    out["ke_ratio_eq2"] = math.exp(-2.0 * nu * k2 * T)
+    return out
+
+
+# --------------------------------------------------------------------- W2 --
+def _vorticity(u, n):
+    ux, uy = u[0].reshape(n, n), u[1].reshape(n, n)  # [y, x]
+    dvy_dx = (torch.roll(uy, -1, 1) - torch.roll(uy, 1, 1)) * 0.5
+    dux_dy = (torch.roll(ux, -1, 0) - torch.roll(ux, 1, 0)) * 0.5
+    return (dvy_dx - dux_dy).reshape(-1)
+
+
+def w2(steps=20000, every=100, snap_every=1000):
+    n = 1024
+    beta = Wk.shear_beta(n)
+    rho, u = Wk.shear_layer(n)
+    out = {"experiment": "w2", "workload": f"D2Q9 shear layer {n}^2, u0 = 0.04, kappa = 80, "
+           f"delta = 0.05, Re = 3e4 (beta = {beta:.6f}), FP32 storage, {steps} steps",
+           "beta": beta}
+    with elbm.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f32", beta=beta) as sim:
+        sim.step(20)
+        ms = _timed_steps(sim, 2000)
+    out["ms_per_step"] = ms
+    out["mlups"] = n * n / ms / 1e3
+    out["gbs_algorithmic"] = 2 * 9 * 4 * n * n / ms / 1e6
+    curve, snaps = [], []
+    diag = elbm.DIAG_ALPHA | elbm.DIAG_COUNTS | elbm.DIAG_SUMS
+    with elbm.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f32", beta=beta,
+                         diag=diag) as sim:
+        H0 = None
+        for t in range(every, steps + 1, every):
+            sim.step(every)
+            st = sim.stats()
+            if H0 is None:
+                H0 = st["sum_H"]
+            curve.append([t, st["n_alpha_lt2"] / (n * n), st["n_accept2"] / (n * n),
+                          st["alpha_min"], st["sum_H"]])
+            if t % snap_every == 0:
+                a = sim.alpha_field()
+                r, v = sim.moments()
+                w = _vorticity(v, n).abs()
+                dev = 2.0 - a
+                c = torch.corrcoef(torch.stack([dev, w]))[0, 1].item()
+                snaps.append({"t": t, "alpha_min": a.min().item(),
+                              "frac_alpha_lt2": (a < 2.0).double().mean().item(),
+                              "corr_2_minus_alpha_abs_vorticity": c,
+                              "kinetic_energy": _kinetic(r, v)})
+                log(f"w2 t={t}: {snaps[-1]}")
+    fr = np.array([c[1] for c in curve])
+    Hs = np.array([c[4] for c in curve])
+    out.update({"fraction_alpha_lt2": {"mean": float(fr.mean()), "min": float(fr.min()),
+                                       "max": float(fr.max()), "last": float(fr[-1])},
+                "sum_H_increases": int((np.diff(Hs) > 0).sum()),
+                "sum_H_checks": int(len(Hs) - 1),
+                "curve_every_1000": [c for c in curve if c[0] % 1000 == 0],
+                "snapshots": snaps})
+    return out
+
+
+# --------------------------------------------------------------------- E2 --
+def e2():
+    n, T, nu = 128, 3200, 1e-5
+    beta = Wk.beta_from_nu(nu)
+    rho, u = Wk.shear_layer(n)
+    out = {"experiment": "e2", "workload": f"D2Q9 shear layer {n}^2, nu = 1e-5 "
+           f"(beta = {beta:.8f}), FP64 storage, {T} steps (t = 1)"}
+    p = []
+    with elbm.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f64", beta=beta,
+                         diag=elbm.DIAG_COUNTS) as sim:
+        for t in range(1, T + 1):
+            sim.step(1)
+            p.append(sim.stats()["n_accept2"] / (n * n))
+    p = np.array(p)
+    tt = np.arange(1, T + 1) / T
+    late = p[tt >= 0.25]
+    out.update({"proportion_mean_t_ge_0.25": float(late.mean()),
+                "proportion_min_t_ge_0.25": float(late.min()),
+                "proportion_max_t_ge_0.25": float(late.max()),
+                "proportion_at": {f"{x:.2f}": float(p[int(x * T) - 1])
+                                  for x in (0.1, 0.25, 0.5, 0.75, 1.0)},
+                "paper": "around 0.5 for most of the time (Fig. 5 discussion)"})
+    return out
+
+
+# --------------------------------------------------------------------- W4 --
+def _H_site(f, W):
+    return (f * torch.log(f / W[:, None])).sum(0)
+
+
+def w4(n=256, T=2000):
+    beta = Wk.tgv3d_beta(n)
+    rho, u = Wk.taylor_green_3d(n)
+    N = n ** 3
+    L = [(a, b, c) for c in (0, 1, -1) for b in (0, 1, -1) for a in (0, 1, -1)]
+    wa = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+    W = torch.tensor([wa[a] * wa[b] * wa[c] for a, b, c in L], dtype=torch.float64,
+                     device="cuda")
+    ulp = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f32dev": 2.0 ** -24, "f16dev": 2.0 ** -11}
+    cases = [("f64", True), ("f32", True), ("f32dev", True), ("f16dev", True),
+             ("f32", False), ("f16dev", False)]
+    out = {"experiment": "w4", "workload": f"D3Q27 Taylor-Green {n}^3, u0 = 0.05, Re = 1600 "
+           f"(beta = {beta:.6f}), {T} steps, closed-form alpha", "cases": {}}
+    ref = None
+    sites = torch.arange(N, dtype=torch.int64, device="cuda")
+    for storage, fp64 in cases:
+        name = f"{storage}/{'fp64' if fp64 else 'fp32'}-arith"
+        with elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, storage=storage, fp64=fp64,
+                             beta=beta, diag=elbm.DIAG_COUNTS | elbm.DIAG_SUMS) as sim:
+            Hsum, neg = [], 0
+            for t in range(0, T, 100):
+                sim.step(100)
+                st = sim.stats()
+                Hsum.append(st["sum_H"])
+                neg = max(neg, st["n_negative"])
+            r, v = sim.moments()
+            ke = _kinetic(r, v)
+            # per-site H balance of one more step: pre-collision f(x,T) vs the
+            # stored post-collision value written at x
+            f0 = sim.populations()
+            sim.step(1)
+            f1 = sim.gather(sites, 1)
+            torch.cuda.synchronize()
+            dH = _H_site(f1, W) - _H_site(f0, W)
+            tauH = 8 * 2.0 ** -52 * r * torch.clamp(
+                (f0 / r * torch.log(f0 / W[:, None]).abs()).sum(0), min=1.0)
+            # change of H from rounding each stored value to the storage format
+            if storage.endswith("dev"):
+                # s = f/W - rho_ref is rounded: |df| <= W ulp(|s|) / 2, with
+                # FP16's subnormal spacing as the floor
+                s = (f1 / W[:, None] - 1.0).abs()
+                df = W[:, None] * torch.clamp(s, min=2.0 ** -14) * ulp[storage]
+            else:
+                df = f1.abs() * ulp[storage]
+            tauS = ((torch.log(f1 / W[:, None]) + 1.0).abs() * df).sum(0)
+            inc_fp64 = int((dH > tauH).sum())
+            inc_round = int((dH > tauH + tauS).sum())
+            del f0, f1, dH, tauH, tauS, df
+            res = {"kinetic_energy": ke, "negative_population_sites_max": neg,
+                   "sum_H_increases_per_100_steps": int((np.diff(Hsum) > 0).sum()),
+                   "site_H_increase_beyond_fp64_tol": inc_fp64,
+                   "site_H_increase_beyond_storage_rounding": inc_round}
+            if ref is None:
+                ref = (r.clone(), v.clone(), ke)
+            else:
+                du = (v - ref[1]).abs()
+                umax = ref[1].abs().max().item()
+                res.update({"u_linf_rel": du.max().item() / umax,
+                            "u_l2_rel": (du.pow(2).sum().sqrt() /
+                                         ref[1].pow(2).sum().sqrt()).item(),
+                            "ke_rel_err": (ke - ref[2]) / ref[2],
+                            "rho_linf": (r - ref[0]).abs().max().item()})
+            del r, v
+            torch.cuda.empty_cache()
+        out["cases"][name] = res
+        log(f"w4 {name}: {res}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4"])
+    ap.add_argument("--w2-steps", type=int, default=20000)
+    args = ap.parse_args()
+    if not torch.cuda.is_available():
+        print("experiments.py needs a GPU", file=sys.stderr)
+        return 1
+    elbm.lib()
+    for w in args.which:
+        t0 = time.time()
+        res = {"w1": w1, "e2": e2, "w4": w4}.get(w, lambda: w2(args.w2_steps))()
+        res["wall_s"] = round(time.time() - t0, 1)
+        print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
