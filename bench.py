@@ -111,11 +111,24 @@ def cpu_baseline(n_full, beta, budget_s=10.0):
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 200:
             break
-    return {"value": round(m ** 3 * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
+    closed = m ** 3 * steps / el / 1e6
+    # the Newton comparison on the same state, for a third of the budget
+    cfgn = oracle.Config(D=3, nx=m, ny=m, nz=m, beta=beta, mode="newton", nthreads=cores)
+    nsteps, t0 = 0, time.perf_counter()
+    while True:
+        f, _, _ = oracle.step(cfgn, f)
+        nsteps += 1
+        eln = time.perf_counter() - t0
+        if eln >= budget_s / 3 or nsteps >= 100:
+            break
+    newton = m ** 3 * nsteps / eln / 1e6
+    return {"value": round(closed, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"D3Q27 Taylor-Green {m}^3 (of the {n_full}^3 workload), closed-form "
                       f"alpha, FP64, {steps} steps in {el:.1f} s on {cores} threads "
-                      f"({platform.processor() or platform.machine()})"}
+                      f"({platform.processor() or platform.machine()}); then Newton alpha, "
+                      f"{nsteps} steps in {eln:.1f} s",
+            "newton_value": round(newton, 3), "closed_over_newton": round(closed / newton, 2)}
 
 
 def _serving_summary(res, rate):
