@@ -12,7 +12,10 @@ constexpr int kBlock = 256;        // threads per workgroup of the step kernel
 // Tiles of kBlock sites per step workgroup: two for 2- and 4-byte storage
 // (the second tile's loads overlap the first tile's arithmetic), one for
 // FP64 storage (two would not fit the register file at two waves per SIMD).
-constexpr int tiles_per_block(int elem_bytes) { return elem_bytes < 8 ? 2 : 1; }
+#ifndef ELBM_TILES_NARROW
+#define ELBM_TILES_NARROW 2
+#endif
+constexpr int tiles_per_block(int elem_bytes) { return elem_bytes < 8 ? ELBM_TILES_NARROW : 1; }
 constexpr int kMaxBatch = 16;      // simulations per batched launch
 constexpr int kCountBytes = 48;    // per-workgroup counts record
 constexpr int kSumBytes = 64;      // per-workgroup sums record

@@ -224,6 +224,24 @@ struct SeriesK {
     E = pe * t;
     O = po * t * x;
   }
+  // sE += f E(x), sO += f O(x), the K-term sums scaled as for eval(), with
+  // f x^2 formed once for both: one multiplication fewer per direction.
+  __device__ __forceinline__ void accum(R x, R f, R& sE, R& sO) const {
+    const R t = x * x;
+    R pe = R(1), po = R(1);
+    if constexpr (K >= 2) {
+      pe = t + e[K - 2];
+      po = t + o[K - 2];
+    }
+#pragma unroll
+    for (int k = K - 2; k >= 1; --k) {
+      pe = fma(pe, t, e[k - 1]);
+      po = fma(po, t, o[k - 1]);
+    }
+    const R w = f * t;
+    sE = fma(w, pe, sE);
+    sO = fma(w * x, po, sO);
+  }
 };
 
 template <class R, int K>

@@ -41,6 +41,18 @@ __device__ __forceinline__ R opaque(R v) {
   return v;
 }
 
+// Scheduling fence every ELBM_SCHED_GROUP directions of an unrolled pass
+// (0: none): keeps the scheduler from hoisting the loads and conversions of
+// many directions at once, which would hold their registers live.
+#ifndef ELBM_SCHED_GROUP
+#define ELBM_SCHED_GROUP 0
+#endif
+__device__ __forceinline__ void sched_group(int i) {
+  if (ELBM_SCHED_GROUP > 0 && i % (ELBM_SCHED_GROUP > 0 ? ELBM_SCHED_GROUP : 1) ==
+                                  (ELBM_SCHED_GROUP > 0 ? ELBM_SCHED_GROUP : 1) - 1)
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // The stored population widened to the arithmetic type.  FP32 -> FP64 goes
 // through a volatile asm conversion: the compiler can neither merge the
 // conversions of different passes (which would keep Q doubles live) nor needs
@@ -66,6 +78,10 @@ __device__ __forceinline__ auto widen(T v) {
 template <class R>
 __device__ __forceinline__ R sel3(const R (&a)[3], int d) {
   return d == 0 ? a[0] : (d == 1 ? a[1] : a[2]);
+}
+template <class R>
+__device__ __forceinline__ R sel9(const R (&a)[3][3], int dx, int dy) {
+  return sel3(a[0], dy) * R(dx == 0) + sel3(a[1], dy) * R(dx == 1) + sel3(a[2], dy) * R(dx == 2);
 }
 
 // Series lengths of the three tiers and their validity bounds on
@@ -173,10 +189,11 @@ struct Site {
   T raw[Q];
   R rho, irho, rho_ref;
   R u[3];
-  R e[3][3];   // e[a][d]  = w(c) A_a z_a^c   (digit d of c)
-  R ie[3][3];  // ie[a][d] = 1 / e[a][d]
-  R f01[3][3]; // rho e[0][dx] e[1][dy]:  f^eq_i = f01[dx][dy] e[2][dz]
-  R r01[3][3]; // ie[0][dx] ie[1][dy] / rho: 1/f^eq_i = r01[dx][dy] ie[2][dz]
+  // With e[a][d] = w(c) A_a z_a^c (digit d of c) and ie[a][d] = 1/e[a][d]
+  // of the equilibrium's per-axis factors, the site keeps only
+  R f01[3][3]; // rho e[0][dx] e[1][dy]:  f^eq_i = f01[dx][dy] e2[dz]
+  R r01[3][3]; // ie[0][dx] ie[1][dy] / rho: 1/f^eq_i = r01[dx][dy] ie2[dz]
+  R e2[3], ie2[3];  // e[2][dz], ie[2][dz]
   // where the populations came from, for the loops of the rare paths
   const T* src;
   int64_t pitch;
@@ -199,8 +216,8 @@ struct Site {
     Pass p;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      p.e2[k] = opaque(e[2][k]);
-      p.ie2[k] = opaque(ie[2][k]);
+      p.e2[k] = opaque(e2[k]);
+      p.ie2[k] = opaque(ie2[k]);
     }
     return p;
   }
@@ -212,21 +229,28 @@ struct Site {
     const R q = r01[L::dg(i, 0)][L::dg(i, 1)];
     return fma(g(i), D > 2 ? q * p.ie2[L::dg(i, 2)] : q, R(-1));
   }
-  __device__ __forceinline__ void fold() {
+  // The x- and y-axis factors are folded with rho into f01 / r01 and not
+  // kept, which saves 12 doubles of registers over the whole update.
+  __device__ __forceinline__ void fold(const Equilibrium<R, D>& eq) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        f01[a][b] = rho * (e[0][a] * e[1][b]);
-        r01[a][b] = irho * (ie[0][a] * ie[1][b]);
+        f01[a][b] = rho * (eq.e[0][a] * eq.e[1][b]);
+        r01[a][b] = irho * (eq.ie[0][a] * eq.ie[1][b]);
       }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      e2[k] = eq.e[2][k];
+      ie2[k] = eq.ie[2][k];
+    }
   }
 
   // -- loop accessors (run-time, wavefront-uniform i) -----------------------
   // Register arrays are never indexed at run time (that would move them to
   // scratch memory); the population is re-read from the source buffer,
   // whose lines this wavefront has just brought into the caches.
-  __device__ __forceinline__ void xfe(int i, R& xi, R& fi) const {
+  __device__ __forceinline__ void xfe(int i, R& xi, R& fi, R* gout = nullptr) const {
     const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
     const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
     const R W = R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0) / R(L::den());
@@ -234,9 +258,10 @@ struct Site {
     const T gv = *(const gptr<T>)((gaddr)(uintptr_t)src + (uint64_t)i * (uint64_t)pitch * sizeof(T) +
                                    off * (uint32_t)sizeof(T));
     const R gi = Codec<S, R>::dec(gv, W, rho_ref);
-    fi = rho * (sel3(e[0], dx) * sel3(e[1], dy)) * sel3(e[2], dz);
-    const R ri = irho * (sel3(ie[0], dx) * sel3(ie[1], dy)) * sel3(ie[2], dz);
+    fi = sel9(f01, dx, dy) * sel3(e2, dz);
+    const R ri = sel9(r01, dx, dy) * sel3(ie2, dz);
     xi = fma(gi, ri, R(-1));
+    if (gout) *gout = gi;
   }
 };
 
@@ -277,13 +302,12 @@ __device__ __forceinline__ void rare_sums(const Site<D, S, R>& v, R astar, bool 
   constexpr int Q = Site<D, S, R>::Q;
   if (star2 && xabs <= Base<R>::thrL) {
     R sE = R(0), sO = R(0);
+    const SeriesK<R, Base<R>::KL> ser;
 #pragma unroll 1
     for (int i = 0; i < Q; ++i) {
-      R xi, fi, E, O;
+      R xi, fi;
       v.xfe(i, xi, fi);
-      series_EO<R, Base<R>::KL>(xi, E, O);
-      sE += fi * E;
-      sO += fi * O;
+      ser.accum(xi, fi, sE, sO);
     }
     R cE, cO;
     series_scale<R, Base<R>::KL>(cE, cO);
@@ -313,22 +337,31 @@ __device__ __forceinline__ void rare_sums(const Site<D, S, R>& v, R astar, bool 
 template <class R>
 struct AlphaOut {
   R alpha, D;
-  bool accepted2, astar_lt2, guard, fallback;
+  bool accepted2, astar_lt2, guard, fallback, deferred;
   int iters;
 };
 
+// Phases of the closed form.  kPhaseAll evaluates every tier in one call.
+// kPhaseCommon evaluates the short-series tiers and defers the lanes that
+// need the rare tier (alpha_* < 2, or max|x_i| beyond the middle tier);
+// kPhaseRare then handles only those lanes, after the common phase's values
+// have died, so the long series and the logarithms do not raise the
+// register peak of the common path.
+enum { kPhaseAll = 0, kPhaseCommon = 1, kPhaseRare = 2 };
+
 // The choice of alpha at one site (all lanes of the wavefront call it).
-template <int MODE, int D, class S, class R>
+template <int MODE, int PHASE, int D, class S, class R>
 __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimDesc& d) {
   constexpr int Q = Site<D, S, R>::Q;
   AlphaOut<R> o;
+  o.deferred = false;
   // The root solvers need alpha_max on every lane; the closed form and the
   // secant need it only where alpha_* < 2, which the tiers below detect.
   constexpr bool kXmax = (MODE == kNewton || MODE == kBisect);
   if constexpr (MODE == kNewton || MODE == kBisect || MODE == kSecant) v.w = locate<D>(d, v.site);
   // Common tier: x_i, max|x_i| and the K-term series sums in one pass.
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
-  {
+  if constexpr (PHASE != kPhaseRare) {
   const SeriesK<R, Base<R>::K> ser;
   const auto P = v.pass();
 #pragma unroll
@@ -336,18 +369,24 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
     const R xi = v.x(i, P);
     if (kXmax) xmax = fmax(xmax, xi);
     xabs = fmax(xabs, fabs(xi));
-    R E, O;
-    ser.eval(xi, E, O);
-    const R fi = v.fe(i, P);
-    sE = fma(fi, E, sE);
-    sO = fma(fi, O, sO);
+    ser.accum(xi, v.fe(i, P), sE, sO);
+    sched_group(i);
   }
   }
-  {
+  if constexpr (PHASE != kPhaseRare) {
     R cE, cO;
     series_scale<R, Base<R>::K>(cE, cO);
     sE *= cE;
     sO *= cO;
+  } else {
+    // only deferred lanes are active: max|x_i| again, by the loop accessors
+    v.w = locate<D>(d, v.site);
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      R xi, fi;
+      v.xfe(i, xi, fi);
+      xabs = fmax(xabs, fabs(xi));
+    }
   }
   // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
   // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
@@ -356,18 +395,21 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   const bool common = xabs <= Base<R>::thr;
   const bool mid = !common && xabs <= Base<R>::thrM;
   const bool rare = !(xabs <= Base<R>::thrM);
-  if (__any(mid)) {
+  if constexpr (PHASE == kPhaseCommon) {
+    if (rare) {
+      o.deferred = true;
+      o.alpha = R(2);
+      o.D = R(0);
+      o.accepted2 = o.astar_lt2 = o.guard = o.fallback = false;
+      o.iters = 0;
+    }
+  }
+  if (PHASE != kPhaseRare && __any(mid)) {
     R mE = R(0), mO = R(0);
     const SeriesK<R, Base<R>::KM> ser;
     const auto P = v.pass();
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      R E, O;
-      ser.eval(v.x(i, P), E, O);
-      const R fi = v.fe(i, P);
-      mE = fma(fi, E, mE);
-      mO = fma(fi, O, mO);
-    }
+    for (int i = 0; i < Q; ++i) ser.accum(v.x(i, P), v.fe(i, P), mE, mO);
     R cE, cO;
     series_scale<R, Base<R>::KM>(cE, cO);
     mE *= cE;
@@ -378,7 +420,10 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
       Gs = R(2) * mO;
     }
   }
-  if (__any(rare) && !kXmax) v.w = locate<D>(d, v.site);
+  if constexpr (PHASE == kPhaseCommon) {
+    if (rare) return o;
+  }
+  if (PHASE == kPhaseAll && __any(rare) && !kXmax) v.w = locate<D>(d, v.site);
   if (rare && !kXmax) {
     xmax = R(-1);
 #pragma unroll 1
@@ -500,8 +545,10 @@ struct Acc {
     amax = -INFINITY;
     rho = j[0] = j[1] = j[2] = H = 0.0;
   }
-  __device__ __forceinline__ void count(int k, bool pred) {
-    c[k] += (uint32_t)__popcll(__ballot(pred));
+  // wavefront counts of the count predicates; all lanes must be active
+  __device__ __forceinline__ void count_flags(uint32_t flags) {
+#pragma unroll
+    for (int k = 0; k < kCntIters; ++k) c[k] += (uint32_t)__popcll(__ballot((flags >> k) & 1u));
   }
 };
 
@@ -607,14 +654,124 @@ __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32
   }
 }
 
+// rho and rho u of a site, summed per x-row of directions first: for each
+// (c_y, c_z) the three directions c_x = 0, +1, -1 give a row sum and an
+// x-momentum term.
+template <int D, class S, class R>
+__device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (&j)[3]) {
+  rho = R(0);
+  j[0] = j[1] = j[2] = R(0);
+  R rs[3][3], rx[3][3];
+#pragma unroll
+  for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz)
+#pragma unroll
+    for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+      const int i0 = 9 * dz + 3 * dy;
+      const R g0 = v.g(i0), gp = v.g(i0 + 1), gm = v.g(i0 + 2);
+      rs[dy][dz] = g0 + (gp + gm);
+      rx[dy][dz] = gp - gm;
+    }
+#pragma unroll
+  for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) {
+    R cz = R(0);
+#pragma unroll
+    for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+      cz += rs[dy][dz];
+      j[0] += rx[dy][dz];
+    }
+    rho += cz;
+    if (D > 2) j[2] += (dz == 1) ? cz : (dz == 2 ? -cz : R(0));
+  }
+  if (D > 1) {
+#pragma unroll
+    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) j[1] += rs[1][dz] - rs[2][dz];
+  }
+}
+
+// Loads (or takes) the site's populations, forms rho, u and, for the
+// entropic modes, the equilibrium factors.
+template <int D, class S, class R>
+__device__ __forceinline__ void site_prepare(Site<D, S, R>& v, const SimDesc& d,
+                                             const typename S::T* src, uint32_t sl, R& rho,
+                                             R (&j)[3], bool equilibrium) {
+  v.src = src;
+  v.pitch = d.pitch;
+  v.site = sl;
+  v.desc = &d;
+  v.rho_ref = (R)d.rho_ref;
+  site_moments(v, rho, j);
+  const R irho = R(1) / rho;
+  v.rho = rho;
+  v.irho = irho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v.u[a] = j[a] * irho;
+  if (equilibrium) {
+    Equilibrium<R, D> eq;
+    eq.build(v.u);
+    v.fold(eq);
+  }
+}
+
+// Count predicates of one site as bits kCnt*: they are turned into
+// wavefront counts by ballots where all lanes of the wavefront are active.
+__device__ __forceinline__ uint32_t flag(int k, bool p) { return p ? (1u << k) : 0u; }
+
+struct SiteOut {
+  bool deferred;   // left to the rare phase (closed form)
+  uint32_t flags;  // count predicates (bits kCnt*)
+};
+
+// Diagnostics of one updated site of an entropic mode: per-lane values
+// here, count predicates returned.
+template <int D, class S, class R, bool SUMS>
+__device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bool live,
+                                            const Site<D, S, R>& v, const AlphaOut<R>& ao,
+                                            R ftmin, const R (&j)[3], Acc& acc, int diag) {
+  const R alpha = ao.alpha, rho = v.rho;
+  uint32_t flags = 0;
+  if (diag & kDiagCounts) {
+    if (live)
+      flags = flag(kCntAccept2, ao.accepted2) | flag(kCntAstarLt2, ao.astar_lt2) |
+              flag(kCntAlphaLt2, alpha < R(2)) | flag(kCntGuard, ao.guard) |
+              flag(kCntFallback, ao.fallback) | flag(kCntNeg, ftmin < R(0)) |
+              flag(kCntNonfinite, !isfinite(rho * alpha * v.u[0] * v.u[1] * v.u[2] + rho));
+    if (live) acc.iters += ao.iters;
+    if (SUMS && live && (diag & kDiagSums)) {
+      // H(f) = H(f^eq) + D, H(f^eq) = rho [ln rho + sum_a (ln A_a + u_a ln z_a)]
+      double h = log((double)rho);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double ua = (double)v.u[a];
+        const double sa = sqrt(1.0 + 3.0 * ua * ua);
+        h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
+      }
+      acc.H += (double)rho * h + (double)ao.D;
+    }
+  }
+  if (diag & kDiagAlpha) d.alpha[s] = (double)alpha;
+  if (live && (diag & kDiagCounts)) {
+    acc.amin = fminf(acc.amin, (float)alpha);
+    acc.amax = fmaxf(acc.amax, (float)alpha);
+    if (SUMS && (diag & kDiagSums)) {
+      acc.rho += (double)rho;
+#pragma unroll
+      for (int a = 0; a < D; ++a) acc.j[a] += (double)j[a];
+    }
+  }
+  return flags;
+}
+
 // One site from its pulled populations: moments, equilibrium, alpha,
 // collision, store of dst_i(x) at the site's own index.  `live` is false for
 // the padding lanes of the last tile: they compute on the values of site 0
 // (so that wavefront-wide votes see ordinary numbers) and store into the
 // plane padding past N, which every plane has up to the next multiple of
 // kBlock sites and which no step reads.
-template <int D, class S, int MODE, class R>
-__device__ __forceinline__ void site_update(const SimDesc& d, const typename S::T* __restrict__ src,
+//
+// PHASE (closed form): kPhaseCommon leaves the lanes that need the rare
+// tier untouched and returns true for them; site_update_rare completes them.
+template <int D, class S, int MODE, class R, bool SUMS, int PHASE = kPhaseAll>
+__device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename S::T* __restrict__ src,
                                             typename S::T* __restrict__ dst, uint32_t s,
                                             bool live, const typename S::T (&raw)[Lattice<D>::Q],
                                             Acc& acc, int diag) {
@@ -625,60 +782,20 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
   const uint32_t sl = live ? s : 0u;  // the site whose values were loaded
 
   Site<D, S, R> v;
-  const int64_t pitch = d.pitch;
-  v.src = src;
-  v.pitch = pitch;
-  v.site = sl;
-  v.desc = &d;
 #pragma unroll
   for (int i = 0; i < Q; ++i) v.raw[i] = raw[i];
-  v.rho_ref = (R)d.rho_ref;
-
-  // Moments, summed per x-row of directions first: for each (c_y, c_z) the
-  // three directions c_x = 0, +1, -1 give a row sum and an x-momentum term.
-  R rho = R(0), j[3] = {R(0), R(0), R(0)};
-  {
-    R rs[3][3], rx[3][3];
-#pragma unroll
-    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz)
-#pragma unroll
-      for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
-        const int i0 = 9 * dz + 3 * dy;
-        const R g0 = v.g(i0), gp = v.g(i0 + 1), gm = v.g(i0 + 2);
-        rs[dy][dz] = g0 + (gp + gm);
-        rx[dy][dz] = gp - gm;
-      }
-#pragma unroll
-    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) {
-      R cz = R(0);
-#pragma unroll
-      for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
-        cz += rs[dy][dz];
-        j[0] += rx[dy][dz];
-      }
-      rho += cz;
-      if (D > 2) j[2] += (dz == 1) ? cz : (dz == 2 ? -cz : R(0));
-    }
-    if (D > 1) {
-#pragma unroll
-      for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) j[1] += rs[1][dz] - rs[2][dz];
-    }
-  }
-  const R irho = R(1) / rho;
-  v.rho = rho;
-  v.irho = irho;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) v.u[a] = j[a] * irho;
+  R rho, j[3];
+  site_prepare(v, d, src, sl, rho, j, MODE != kBGK);
   const R beta = (R)d.beta;
-  R alpha = R(2);
-  R ftmin;
+  const int64_t pitch = d.pitch;
 
   if constexpr (MODE == kBGK) {
     // LBGK: alpha = 2 with the second-order polynomial equilibrium.
     const R* u = v.u;
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R tb = R(2) * beta;
-    ftmin = R(INFINITY);
+    R ftmin = R(INFINITY);
+    uint32_t flags = 0;
     const uint32_t so = s * es;
     const gaddr base = plane_base(dst);
     const uint64_t pb = (uint64_t)pitch * es;
@@ -692,28 +809,30 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
       st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
-      acc.count(kCntNeg, live && ftmin < R(0));
-      acc.count(kCntNonfinite, live && !isfinite(rho * u[0] * u[1] * u[2] + rho));
+      if (live)
+        flags = flag(kCntNeg, ftmin < R(0)) |
+                flag(kCntNonfinite, !isfinite(rho * u[0] * u[1] * u[2] + rho));
     }
-  } else {
-    Equilibrium<R, D> eq;
-    eq.build(v.u);
+    if (diag & kDiagAlpha) d.alpha[s] = 2.0;
+    if (live && (diag & kDiagCounts)) {
+      acc.amin = fminf(acc.amin, 2.0f);
+      acc.amax = fmaxf(acc.amax, 2.0f);
+      if (SUMS && (diag & kDiagSums)) {
+        acc.rho += (double)rho;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        v.e[a][c] = eq.e[a][c];
-        v.ie[a][c] = eq.ie[a][c];
+        for (int a = 0; a < D; ++a) acc.j[a] += (double)j[a];
       }
-    v.fold();
-    const AlphaOut<R> ao = choose_alpha<MODE>(v, d);
-    alpha = ao.alpha;
+    }
+    return SiteOut{false, flags};
+  } else {
+    const AlphaOut<R> ao = choose_alpha<MODE, PHASE>(v, d);
+    if (PHASE == kPhaseCommon && ao.deferred) return SiteOut{true, 0u};
     // Eq. (1): f~_i = f_i + alpha beta (f^eq_i - f_i), in the site
     // arithmetic's precision; the result is rounded once, into the storage
     // format.
-    const R ab = alpha * beta;
+    const R ab = ao.alpha * beta;
     const auto P = v.pass();
-    ftmin = R(INFINITY);
+    R ftmin = R(INFINITY);
     const uint32_t so = s * es;
     const gaddr base = plane_base(dst);
     const uint64_t pb = (uint64_t)pitch * es;
@@ -721,44 +840,56 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
     for (int i = 0; i < Q; ++i) {
       const R gi = v.g(i);
       const R ft = fma(ab, v.fe(i, P) - gi, gi);
-      ftmin = fmin(ftmin, ft);
+      // In the common and middle tiers |x_i| <= 0.025 and 0 < alpha beta < 2,
+      // so f~_i = f^eq_i (1 + (1 - alpha beta) x_i) > 0.975 f^eq_i: no
+      // negative population to look for.
+      if constexpr (PHASE != kPhaseCommon) ftmin = fmin(ftmin, ft);
       // a private copy of the offset per store keeps the address in the
       // scalar-base + vector-offset form (otherwise the common offset is
       // added first and every plane offset costs 64-bit vector arithmetic)
       st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      sched_group(i);
     }
-    if (diag & kDiagCounts) {
-      acc.count(kCntAccept2, live && ao.accepted2);
-      acc.count(kCntAstarLt2, live && ao.astar_lt2);
-      acc.count(kCntAlphaLt2, live && alpha < R(2));
-      acc.count(kCntGuard, live && ao.guard);
-      acc.count(kCntFallback, live && ao.fallback);
-      acc.count(kCntNeg, live && ftmin < R(0));
-      acc.count(kCntNonfinite, live && !isfinite(rho * alpha * v.u[0] * v.u[1] * v.u[2] + rho));
-      if (live) acc.iters += ao.iters;
-      if (live && (diag & kDiagSums)) {
-        // H(f) = H(f^eq) + D, H(f^eq) = rho [ln rho + sum_a (ln A_a + u_a ln z_a)]
-        double h = log((double)rho);
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const double ua = (double)v.u[a];
-          const double sa = sqrt(1.0 + 3.0 * ua * ua);
-          h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
-        }
-        acc.H += (double)rho * h + (double)ao.D;
-      }
-    }
+    return SiteOut{false, record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
   }
-  if (diag & kDiagAlpha) d.alpha[s] = (double)alpha;
-  if (live && (diag & kDiagCounts)) {
-    acc.amin = fminf(acc.amin, (float)alpha);
-    acc.amax = fmaxf(acc.amax, (float)alpha);
-    if (diag & kDiagSums) {
-      acc.rho += (double)rho;
-#pragma unroll
-      for (int a = 0; a < D; ++a) acc.j[a] += (double)j[a];
-    }
+}
+
+// A lane deferred by the common phase: the populations are reloaded (from
+// the caches, which this wavefront has just filled), the moments and the
+// equilibrium recomputed by the same arithmetic, alpha taken from the rare
+// tier, and the collision run as a rolled loop that re-reads each
+// population, so no per-direction array stays live across the logarithms.
+template <int D, class S, int MODE, class R, bool SUMS>
+__device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
+                                                 const typename S::T* __restrict__ src,
+                                                 typename S::T* __restrict__ dst, uint32_t s,
+                                                 bool live, Acc& acc, int diag) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  using T = typename S::T;
+  constexpr uint32_t es = sizeof(T);
+  const uint32_t sl = live ? s : 0u;
+  Site<D, S, R> v;
+  load_site<D>(d, src, sl, v.raw);
+  R rho, j[3];
+  site_prepare(v, d, src, sl, rho, j, true);
+  const AlphaOut<R> ao = choose_alpha<MODE, kPhaseRare>(v, d);
+  const R ab = ao.alpha * (R)d.beta;
+  R ftmin = R(INFINITY);
+  const uint32_t so = s * es;
+  const gaddr base = plane_base(dst);
+  const uint64_t pb = (uint64_t)d.pitch * es;
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    R xi, fi, gi;
+    v.xfe(i, xi, fi, &gi);
+    const R ft = fma(ab, fi - gi, gi);
+    ftmin = fmin(ftmin, ft);
+    const int nz0 = (i % 3 == 0) + (D > 1 && (i / 3) % 3 == 0) + (D > 2 && i / 9 == 0);
+    const R invW = R(L::den()) / R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0);
+    st_nt<T>(base + (uint64_t)i * pb, so, Codec<S, R>::enc(ft, invW, v.rho_ref));
   }
+  return record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
 }
 
 // One workgroup per ELBM_TILES tiles of kBlock consecutive sites; the loads
@@ -771,7 +902,7 @@ __device__ __forceinline__ void site_update(const SimDesc& d, const typename S::
 // the cache lines at their x-edges, then run on the same XCD and L2.  Each
 // simulation's workgroup count is a multiple of 8 and starts at a multiple
 // of 8.
-template <int D, class S, int MODE, class R>
+template <int D, class S, int MODE, class R, bool SUMS>
 __global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs args) {
   using T = typename S::T;
   constexpr int Q = Lattice<D>::Q;
@@ -797,12 +928,49 @@ __global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs a
       const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
       load_site<D>(d, src, s < N ? s : 0u, raw[k]);
     }
+    uint32_t flags = 0;
+    if constexpr (MODE == kClosed) {
+      // the closed form in two phases: the rare tier after the common one
+      bool deferred[ELBM_TILES];
 #pragma unroll
-    for (int k = 0; k < ELBM_TILES; ++k) {
-      const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
-      if (k == 0 || (unit * ELBM_TILES + k) * kBlock < N)
-        site_update<D, S, MODE, R>(d, src, dst, s, s < N, raw[k], acc, diag);
+      for (int k = 0; k < ELBM_TILES; ++k) {
+        const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
+        deferred[k] = false;
+        if (k == 0 || (unit * ELBM_TILES + k) * kBlock < N) {
+          const SiteOut o = site_update<D, S, MODE, R, SUMS, kPhaseCommon>(d, src, dst, s, s < N,
+                                                                           raw[k], acc, diag);
+          deferred[k] = o.deferred;
+          flags = o.flags;
+        }
+        if (ELBM_TILES > 1 && (diag & kDiagCounts)) {
+          acc.count_flags(flags);
+          flags = 0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < ELBM_TILES; ++k) {
+        if (__any(deferred[k])) {
+          uint32_t f = 0;
+          if (deferred[k]) {
+            const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
+            f = site_update_rare<D, S, MODE, R, SUMS>(d, src, dst, s, s < N, acc, diag);
+          }
+          if (diag & kDiagCounts) acc.count_flags(f);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < ELBM_TILES; ++k) {
+        const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
+        if (k == 0 || (unit * ELBM_TILES + k) * kBlock < N)
+          flags = site_update<D, S, MODE, R, SUMS>(d, src, dst, s, s < N, raw[k], acc, diag).flags;
+        if (ELBM_TILES > 1 && (diag & kDiagCounts)) {
+          acc.count_flags(flags);
+          flags = 0;
+        }
+      }
     }
+    if (diag & kDiagCounts) acc.count_flags(flags);
   } else if (!(diag & kDiagCounts)) {
     return;  // padding workgroup
   }
@@ -810,9 +978,17 @@ __global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs a
     store_records<MODE == kNewton || MODE == kBisect || MODE == kSecant>(acc, d, (int)lb);
 }
 
+// The sums of ELBM_DIAG_SUMS (which need logarithms per site) are compiled
+// into a kernel of their own, used when a simulation of the batch asks for
+// them, so that the other kernels do not carry their registers.
 template <int D, class S, int MODE, class R>
 hipError_t launch_step(const BatchArgs& a, int grid, hipStream_t st) {
-  k_step<D, S, MODE, R><<<grid, kBlock, 0, st>>>(a);
+  bool sums = false;
+  for (int k = 0; k < a.n; ++k) sums = sums || (a.d[k].diag & kDiagSums);
+  if (sums)
+    k_step<D, S, MODE, R, true><<<grid, kBlock, 0, st>>>(a);
+  else
+    k_step<D, S, MODE, R, false><<<grid, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
