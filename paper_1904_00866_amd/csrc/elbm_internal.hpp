@@ -9,11 +9,12 @@ namespace elbm {
 
 constexpr int kBlock = 256;        // threads per workgroup of the step kernel
 
-// Tiles of kBlock sites per step workgroup: two for 2- and 4-byte storage
-// (the second tile's loads overlap the first tile's arithmetic), one for
-// FP64 storage (two would not fit the register file at two waves per SIMD).
+// Tiles of kBlock sites per step workgroup.  One: the closed form and LBGK
+// run four waves per SIMD, which hide the memory latency better than a
+// second tile's loads issued ahead within one wave (a build option keeps
+// two for 2- and 4-byte storage).
 #ifndef ELBM_TILES_NARROW
-#define ELBM_TILES_NARROW 2
+#define ELBM_TILES_NARROW 1
 #endif
 constexpr int tiles_per_block(int elem_bytes) { return elem_bytes < 8 ? ELBM_TILES_NARROW : 1; }
 constexpr int kMaxBatch = 16;      // simulations per batched launch

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace elbm {
 
 // ---------------------------------------------------------------- lattice --
@@ -119,6 +121,44 @@ struct Prec<float> {
   __device__ static __forceinline__ float sqrt_(float y) { return ::sqrtf(y); }
 };
 
+// ------------------------------------------------ reciprocal, square root --
+// For arguments in the normal range (the site arithmetic never sees zeros,
+// infinities or subnormals here: rho > 0, 1 <= 1 + 3 u^2 < 4, and the
+// equilibrium's denominators lie in (0, 54) for |u| < 1), the hardware
+// estimates refined by Newton's iteration for 1/y (e = 1 - y r,
+// r <- r + r e, quadratic convergence) and Goldschmidt's iteration for
+// sqrt(y) (g ~ sqrt(y), h ~ 1/(2 sqrt(y)), then residual corrections) give
+// the result to about one unit in the last place without the scaling and
+// special-case handling of the library routines.
+template <class R>
+__device__ __forceinline__ R rcp_n(R y) {
+  if constexpr (std::is_same<R, double>::value) {
+    R r = __builtin_amdgcn_rcp(y);
+    R e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    return fma(r, e, r);
+  } else {
+    return R(1) / y;
+  }
+}
+template <class R>
+__device__ __forceinline__ R sqrt_n(R y) {
+  if constexpr (std::is_same<R, double>::value) {
+    const R r = __builtin_amdgcn_rsq(y);
+    R g = y * r, h = 0.5 * r;
+    const R e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    R d = fma(-g, g, y);
+    g = fma(d, h, g);
+    d = fma(-g, g, y);
+    return fma(d, h, g);
+  } else {
+    return Prec<R>::sqrt_(y);
+  }
+}
+
 // ------------------------------------------------------------ equilibrium --
 // The minimiser of H under mass and momentum is f_i^eq = W_i exp(l0 + l.c_i).
 // With tensor-product weights it factorises per axis a:
@@ -138,11 +178,11 @@ struct Equilibrium {
     for (int a = 0; a < 3; ++a) {
       if (a < D) {
         const R ua = u[a];
-        const R s = Prec<R>::sqrt_(R(1) + R(3) * ua * ua);
+        const R s = sqrt_n<R>(R(1) + R(3) * ua * ua);
         const R A = R(2) - s;
         const R nu = R(2) * ua + s;  // z = nu / de
         const R de = R(1) - ua;
-        const R r = R(1) / (nu * de * A);
+        const R r = rcp_n<R>(nu * de * A);
         const R zp = nu * nu * A * r;  // z
         const R zm = de * de * A * r;  // 1/z
         const R iA = nu * de * r;      // 1/A

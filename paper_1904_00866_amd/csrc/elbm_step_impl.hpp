@@ -26,9 +26,6 @@
 #include "elbm_internal.hpp"
 #include "elbm_site.hpp"
 
-#ifndef ELBM_LB_EXTRA
-#define ELBM_LB_EXTRA
-#endif
 
 namespace elbm {
 
@@ -135,9 +132,41 @@ template <class T>
 __device__ __forceinline__ T ld(gaddr plane, uint32_t boff) {
   return *(const gptr<T>)(plane + boff);
 }
+// Load of one population from a plane of `bytes` bytes as a raw buffer load
+// (scalar descriptor, vector byte offset); an offset past the plane reads 0.
 template <class T>
-__device__ __forceinline__ void st_nt(gaddr plane, uint32_t boff, T v) {
-  __builtin_nontemporal_store(v, (gptr<T>)(plane + boff));
+__device__ __forceinline__ T ld_buf(gaddr plane, uint32_t bytes, uint32_t boff) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(plane), (short)0, (int)bytes, 0x00020000);
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+  } else if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, boff, 0, 0));
+  }
+}
+
+// Non-temporal store of one population into a plane of `bytes` bytes, as a
+// raw buffer store: the plane's descriptor is formed in scalar registers and
+// the site's byte offset is the only vector operand, so a store costs no
+// vector address arithmetic.  An offset at or past `bytes` is discarded by
+// the hardware range check.
+template <class T>
+__device__ __forceinline__ void st_nt(gaddr plane, uint32_t bytes, uint32_t boff, T v) {
+  // word 3: 32-bit data format, the raw-buffer setting of this architecture
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(plane), (short)0, (int)bytes, 0x00020000);
+  constexpr int kNT = 2;  // cache policy: non-temporal
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, kNT);
+  } else if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, boff, 0, kNT);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, boff, 0, kNT);
+  }
 }
 
 // Quotient of s < 2^31 by n < 2^20 through one FP64 multiply: (s + 1/2)/n is
@@ -639,6 +668,44 @@ __device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
   }
 }
 
+// The same when the 64 sites of the wavefront lie in one x-row (nx a
+// multiple of 64): the source row of each (c_y, c_z) is then uniform and
+// goes into the scalar base address, and only the three x positions
+// (x, x - 1, x + 1 with periodic wrap) are per-lane offsets.
+template <int D, class T>
+__device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, uint32_t s,
+                                              T (&raw)[Lattice<D>::Q]) {
+  using L = Lattice<D>;
+  const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
+  // row index of the wavefront (uniform), x per lane
+  const uint32_t row = __builtin_amdgcn_readfirstlane(D == 1 ? 0u : qdiv(s, d.inv_nx));
+  const uint32_t x = s - row * nx;
+  uint32_t ys[3] = {0u, 0u, 0u}, zs[3] = {0u, 0u, 0u};
+  if constexpr (D > 1) {
+    const uint32_t z = D == 3 ? __builtin_amdgcn_readfirstlane(qdiv(row, d.inv_ny)) : 0u;
+    const uint32_t y = row - z * ny;
+    ys[0] = y * nx;
+    ys[1] = (y == 0 ? ny - 1 : y - 1) * nx;
+    ys[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+    const uint32_t nxy = nx * ny;
+    zs[0] = z * nxy;
+    zs[1] = (z == 0 ? nz - 1 : z - 1) * nxy;
+    zs[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+  }
+  uint32_t xo[3];
+  xo[0] = x * (uint32_t)sizeof(T);
+  xo[1] = (x == 0 ? nx - 1 : x - 1) * (uint32_t)sizeof(T);
+  xo[2] = (x == nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T);
+  const gaddr base = plane_base(src);
+  const uint64_t pb = (uint64_t)d.pitch * sizeof(T);
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    // the descriptor starts at the source row; the range is the plane's rest
+    const uint32_t rowoff = (zs[L::dg(i, 2)] + ys[L::dg(i, 1)]) * (uint32_t)sizeof(T);
+    raw[i] = ld_buf<T>(base + i * pb + rowoff, (uint32_t)pb - rowoff, xo[L::dg(i, 0)]);
+  }
+}
+
 // Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
 template <int D, class T>
 __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32_t s,
@@ -700,7 +767,7 @@ __device__ __forceinline__ void site_prepare(Site<D, S, R>& v, const SimDesc& d,
   v.desc = &d;
   v.rho_ref = (R)d.rho_ref;
   site_moments(v, rho, j);
-  const R irho = R(1) / rho;
+  const R irho = rcp_n<R>(rho);
   v.rho = rho;
   v.irho = irho;
 #pragma unroll
@@ -806,7 +873,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
       const R gi = v.g(i);
       const R ft = gi + tb * (fe - gi);
       ftmin = fmin(ftmin, ft);
-      st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt<T>(base + i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
       if (live)
@@ -847,7 +914,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
       // a private copy of the offset per store keeps the address in the
       // scalar-base + vector-offset form (otherwise the common offset is
       // added first and every plane offset costs 64-bit vector arithmetic)
-      st_nt<T>(base + i * pb, opaque(so), Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt<T>(base + i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
       sched_group(i);
     }
     return SiteOut{false, record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
@@ -887,7 +954,7 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
     ftmin = fmin(ftmin, ft);
     const int nz0 = (i % 3 == 0) + (D > 1 && (i / 3) % 3 == 0) + (D > 2 && i / 9 == 0);
     const R invW = R(L::den()) / R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0);
-    st_nt<T>(base + (uint64_t)i * pb, so, Codec<S, R>::enc(ft, invW, v.rho_ref));
+    st_nt<T>(base + (uint64_t)i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, invW, v.rho_ref));
   }
   return record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
 }
@@ -902,8 +969,18 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
 // the cache lines at their x-edges, then run on the same XCD and L2.  Each
 // simulation's workgroup count is a multiple of 8 and starts at a multiple
 // of 8.
+// Waves per SIMD the step kernel is compiled for: four (at most 128 vector
+// registers) for the closed form and LBGK on 2- and 4-byte storage, whose
+// common path fits in that budget, so that four waves per SIMD hide the
+// memory latency; the root solvers and FP64 storage keep the registers
+// they need.
+template <class S, int MODE>
+constexpr int step_waves() {
+  return (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) ? 4 : 1;
+}
+
 template <int D, class S, int MODE, class R, bool SUMS>
-__global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs args) {
+__global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const BatchArgs args) {
   using T = typename S::T;
   constexpr int Q = Lattice<D>::Q;
   constexpr int ELBM_TILES = tiles_per_block(sizeof(T));
@@ -926,7 +1003,10 @@ __global__ void __launch_bounds__(kBlock ELBM_LB_EXTRA) k_step(const BatchArgs a
 #pragma unroll
     for (int k = 0; k < ELBM_TILES; ++k) {
       const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
-      load_site<D>(d, src, s < N ? s : 0u, raw[k]);
+      if (d.nx % 64 == 0)
+        load_site_row<D>(d, src, s < N ? s : 0u, raw[k]);
+      else
+        load_site<D>(d, src, s < N ? s : 0u, raw[k]);
     }
     uint32_t flags = 0;
     if constexpr (MODE == kClosed) {
