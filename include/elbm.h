@@ -37,6 +37,8 @@
  *     simulation state (two population buffers, the optional alpha field and
  *     the diagnostics area) in the caller's buffer of elbm_state_bytes()
  *     bytes, which must stay allocated and untouched until elbm_destroy.
+ *     The state's internal layout is private (populations are kept in
+ *     blocks of 64 sites); the calls below exchange plain SoA arrays.
  *     The library itself calls no hipMalloc; it allocates only the small
  *     host-side handle.
  *   - Every call enqueues work on the stream given to elbm_init and returns
@@ -115,10 +117,7 @@ typedef struct {
   double root_tol;       /* bisection window; the paper uses 1e-13        */
   int32_t root_max_iter; /* cap for Newton / bisection iterations (>= 1)  */
   uint32_t diag;         /* ELBM_DIAG_* mask                              */
-  int32_t plane_pad;     /* extra elements after each population plane
-                            (a plane holds N rounded up to 256 sites);
-                            -1 selects the library default                */
-  int32_t reserved;      /* must be 0                                     */
+  int32_t reserved[2];   /* must be 0                                     */
 } elbm_config;
 
 /* Per-step diagnostics of the most recent step (ELBM_DIAG_COUNTS).  In

@@ -53,7 +53,7 @@ int elem_size(int storage) {
 
 struct Layout {
   int D, Q, esize;
-  int64_t N, pitch;
+  int64_t N, padded;
   int nblocks;
   size_t off_buf[2], off_alpha, off_counts, off_sums, off_misc, total;
 };
@@ -95,8 +95,7 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   if (c->diag & ~7u) return fail(ELBM_EINVAL, "unknown diagnostics bits 0x%x", c->diag);
   if ((c->diag & ELBM_DIAG_SUMS) && !(c->diag & ELBM_DIAG_COUNTS))
     return fail(ELBM_EINVAL, "ELBM_DIAG_SUMS needs ELBM_DIAG_COUNTS");
-  if (c->plane_pad < -1) return fail(ELBM_EINVAL, "plane_pad must be >= -1");
-  if (c->reserved != 0) return fail(ELBM_EINVAL, "reserved must be 0");
+  if (c->reserved[0] != 0 || c->reserved[1] != 0) return fail(ELBM_EINVAL, "reserved must be 0");
   if (!step_launcher(D, c->storage, c->alpha_mode, c->alpha_fp64))
     return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
 
@@ -112,21 +111,14 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   const int64_t ntiles = (N + kBlock - 1) / kBlock;
   const int64_t units = (ntiles + tpb - 1) / tpb;
   L->nblocks = int((units + 7) / 8 * 8);
-  // A plane holds the N sites, padding up to the next multiple of kBlock
-  // sites (the stores of the last tile's idle lanes land there), then
-  // plane_pad more elements, rounded to 256 bytes.  The default pad is one
-  // 256-byte block, so that equal sites of different planes are not a
-  // multiple of a large power of two apart.
-  const int64_t per256 = 256 / es;
-  const int64_t pad = c->plane_pad >= 0 ? c->plane_pad : per256;
+  // Each buffer holds the padded site range (whole tiles of every
+  // workgroup) in the blocked layout of pidx(): padded * Q elements.  Every
+  // address is formed in 64 bits or relative to a row of at most
+  // 2^20 Q elements, so no further size limit applies.
   const int64_t padded = L->nblocks * tpb * kBlock;
-  L->pitch = int64_t(align_up(size_t(padded + pad), size_t(per256)));
-  // The kernels address a plane with 32-bit byte offsets.
-  if (uint64_t(L->pitch) * uint64_t(es) >= (uint64_t(1) << 32))
-    return fail(ELBM_EINVAL, "%lld sites of %d bytes exceed the 4 GiB plane limit",
-                (long long)N, es);
+  L->padded = padded;
   size_t off = 0;
-  const size_t bufbytes = align_up(size_t(L->Q) * size_t(L->pitch) * es, kAlign);
+  const size_t bufbytes = align_up(size_t(L->Q) * size_t(padded) * es, kAlign);
   L->off_buf[0] = off;
   off += bufbytes;
   L->off_buf[1] = off;
@@ -190,7 +182,7 @@ BoxDesc box_of(const elbm_sim* s) {
   b.ny = s->cfg.ny;
   b.nz = s->cfg.nz;
   b.N = s->L.N;
-  b.pitch = s->L.pitch;
+  b.padded = s->L.padded;
   b.rho_ref = s->cfg.rho_ref;
   return b;
 }
@@ -203,7 +195,7 @@ SimDesc desc_of(const elbm_sim* s, int block_begin) {
   d.alpha = (s->cfg.diag & ELBM_DIAG_ALPHA) ? s->alpha : nullptr;
   d.counts = (s->cfg.diag & ELBM_DIAG_COUNTS) ? s->counts : nullptr;
   d.sums = (s->cfg.diag & ELBM_DIAG_SUMS) ? s->sums : nullptr;
-  d.pitch = s->L.pitch;
+  d.padded = s->L.padded;
   d.beta = s->cfg.beta;
   d.rho_ref = s->cfg.rho_ref;
   d.root_tol = s->cfg.root_tol;
@@ -254,7 +246,6 @@ elbm_status elbm_config_default(elbm_config* c, int32_t lattice, int32_t nx, int
   c->root_tol = 1e-13;
   c->root_max_iter = 200;
   c->diag = 0;
-  c->plane_pad = -1;
   return ELBM_OK;
 }
 

@@ -75,7 +75,7 @@ __global__ void k_scatter(const BoxDesc b, typename S::T* __restrict__ buf,
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    buf[i * b.pitch + upstream<D>(b, c, i)] =
+    buf[pidx<Q>(upstream<D>(b, c, i), i)] =
         Codec<S, double>::enc(fv[i], L::invW(i), b.rho_ref);
 }
 
@@ -96,7 +96,7 @@ __global__ void k_gather(const BoxDesc b, const typename S::T* __restrict__ buf,
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int64_t src = which == 0 ? upstream<D>(b, c, i) : s;
-    out[i * n + k] = Codec<S, double>::dec(buf[i * b.pitch + src], L::W(i), b.rho_ref);
+    out[i * n + k] = Codec<S, double>::dec(buf[pidx<Q>(src, i)], L::W(i), b.rho_ref);
   }
 }
 
@@ -111,7 +111,7 @@ __global__ void k_moments(const BoxDesc b, const typename S::T* __restrict__ buf
   double r = 0.0, j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double g = Codec<S, double>::dec(buf[i * b.pitch + upstream<D>(b, c, i)], L::W(i), b.rho_ref);
+    const double g = Codec<S, double>::dec(buf[pidx<Q>(upstream<D>(b, c, i), i)], L::W(i), b.rho_ref);
     r += g;
     for (int a = 0; a < D; ++a) j[a] += L::c(i, a) * g;
   }

@@ -30,17 +30,31 @@ constexpr int kStoreF64 = 0, kStoreF32 = 1, kStoreF32Dev = 2, kStoreF16Dev = 3;
 // Alpha modes (same values as ELBM_ALPHA_*).
 constexpr int kClosed = 0, kNewton = 1, kBisect = 2, kBGK = 3, kSecant = 4;
 
-// One simulation as the step kernel sees it.  Populations are SoA planes of
-// `pitch` elements: element (i, s) of a buffer is at buf[i * pitch + s].
-// The step kernel reads `src` (post-collision values of the previous step;
-// pulling src_i(x - c_i) gives f_i(x, t)) and writes `dst` at each site.
+// Population layout of a buffer: blocks of kLane = 64 consecutive sites
+// (one wavefront's sites), each block holding its Q directions one after
+// another as kLane values:
+//   element (i, s) is at ((s / 64) Q + i) 64 + s % 64.
+// A wavefront then reads and writes Q contiguous runs inside one block of
+// 64 Q elements instead of Q runs spread over Q separate planes, which the
+// memory system serves markedly faster.  A buffer holds the padded site
+// range (whole workgroup tiles), so the idle lanes of the last tile write
+// into blocks that no step reads.
+constexpr int kLane = 64;
+template <int Q>
+__host__ __device__ __forceinline__ uint64_t pidx(uint64_t s, int i) {
+  return ((s >> 6) * (uint64_t)Q + (uint64_t)i) * (uint64_t)kLane + (s & 63u);
+}
+
+// One simulation as the step kernel sees it.  The step kernel reads `src`
+// (post-collision values of the previous step; pulling src_i(x - c_i)
+// gives f_i(x, t)) and writes `dst` at each site.
 struct SimDesc {
   const void* src;
   void* dst;
   double* alpha;    // alpha(x) of this step, or nullptr
   void* counts;     // nblocks CountRec records, or nullptr
   void* sums;       // nblocks SumRec records, or nullptr
-  int64_t pitch;
+  int64_t padded;   // sites in the buffers (a multiple of the tile size)
   double beta, rho_ref, root_tol;
   double inv_nx, inv_ny;     // 1/nx, 1/ny for the site-coordinate quotients
   int32_t nx, ny, nz, rows;  // rows = ny * nz x-rows of nx sites
@@ -87,11 +101,11 @@ StepLauncher step_launcher_d1(int storage, int mode, int fp64);
 StepLauncher step_launcher_d2(int storage, int mode, int fp64);
 StepLauncher step_launcher_d3(int storage, int mode, int fp64);
 
-// Auxiliary kernels: layout of `state` as in SimDesc (pitch, buffer `buf`).
+// Auxiliary kernels: a population buffer `buf` in the layout of pidx().
 struct BoxDesc {
   int D, storage;
   int32_t nx, ny, nz;
-  int64_t N, pitch;
+  int64_t N, padded;
   double rho_ref;
 };
 hipError_t launch_validate_init(const BoxDesc& b, const double* rho0, const double* u0,

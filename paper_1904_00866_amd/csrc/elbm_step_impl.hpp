@@ -113,51 +113,48 @@ struct Base<float> {
   static constexpr float thrL = 0.30f;
 };
 
-// Plane addressing.  A plane's base is uniform (scalar registers) and a
-// site's byte offset in it a 32-bit vector register, so loads and stores
-// take the scalar-base + vector-offset form.  The buffer base is passed
-// through in_sgpr() once per tile: the Q plane bases are then formed per
-// tile with scalar adds instead of being held (2 Q scalar registers) across
-// the whole kernel; the explicit global address space keeps the accesses
-// global rather than generic.
+// Addressing.  Bases are uniform (scalar registers) and a lane's byte
+// offset a 32-bit vector register, so loads and stores take the
+// scalar-base + vector-offset form.  The buffer base is passed through
+// in_sgpr() once per tile and the per-direction bases are formed with
+// scalar adds; the explicit global address space keeps the accesses global
+// rather than generic.
 using gaddr = uint64_t;
 template <class T>
 using gptr = __attribute__((address_space(1))) T*;
 
 template <class T>
-__device__ __forceinline__ gaddr plane_base(const T* buf) {
+__device__ __forceinline__ gaddr buffer_base(const T* buf) {
   return in_sgpr((gaddr)(uintptr_t)buf);
 }
-template <class T>
-__device__ __forceinline__ T ld(gaddr plane, uint32_t boff) {
-  return *(const gptr<T>)(plane + boff);
+// Load of one population as a raw buffer load from a range of `bytes`
+// bytes at `base` (scalar descriptor, vector byte offset); an offset past
+// the range reads 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(gaddr base, uint32_t bytes) {
+  // word 3: 32-bit data format, the raw-buffer setting of this architecture
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
 }
-// Load of one population from a plane of `bytes` bytes as a raw buffer load
-// (scalar descriptor, vector byte offset); an offset past the plane reads 0.
+// soff: a uniform byte offset added to the base (scalar operand)
 template <class T>
-__device__ __forceinline__ T ld_buf(gaddr plane, uint32_t bytes, uint32_t boff) {
-  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-      reinterpret_cast<void*>(plane), (short)0, (int)bytes, 0x00020000);
+__device__ __forceinline__ T ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t boff, uint32_t soff) {
   if constexpr (sizeof(T) == 8) {
-    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, boff, soff, 0));
   } else if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, boff, soff, 0));
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, boff, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, boff, soff, 0));
   }
 }
 
-// Non-temporal store of one population into a plane of `bytes` bytes, as a
-// raw buffer store: the plane's descriptor is formed in scalar registers and
-// the site's byte offset is the only vector operand, so a store costs no
-// vector address arithmetic.  An offset at or past `bytes` is discarded by
-// the hardware range check.
+// Non-temporal store of one population into a range of `bytes` bytes at
+// `base`, as a raw buffer store: the descriptor is formed in scalar
+// registers and the lane's byte offset is the only vector operand, so a
+// store costs no vector address arithmetic.  An offset at or past `bytes`
+// is discarded by the hardware range check.
 template <class T>
-__device__ __forceinline__ void st_nt(gaddr plane, uint32_t bytes, uint32_t boff, T v) {
-  // word 3: 32-bit data format, the raw-buffer setting of this architecture
-  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-      reinterpret_cast<void*>(plane), (short)0, (int)bytes, 0x00020000);
+__device__ __forceinline__ void st_nt(gaddr base, uint32_t bytes, uint32_t boff, T v) {
+  const __amdgpu_buffer_rsrc_t r = rsrc(base, bytes);
   constexpr int kNT = 2;  // cache policy: non-temporal
   if constexpr (sizeof(T) == 8) {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -167,6 +164,15 @@ __device__ __forceinline__ void st_nt(gaddr plane, uint32_t bytes, uint32_t boff
   } else {
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, boff, 0, kNT);
   }
+}
+
+// Byte address of the block that holds the wavefront's 64 sites in `buf`
+// (the sites of a wavefront are 64 consecutive, 64-aligned indices, so the
+// block is uniform).
+template <int Q, class T>
+__device__ __forceinline__ gaddr block_base(const T* buf, uint32_t s) {
+  const uint32_t blk = __builtin_amdgcn_readfirstlane(s >> 6);
+  return buffer_base(buf) + (uint64_t)blk * ((uint64_t)Q * kLane * sizeof(T));
 }
 
 // Quotient of s < 2^31 by n < 2^20 through one FP64 multiply: (s + 1/2)/n is
@@ -225,7 +231,6 @@ struct Site {
   R e2[3], ie2[3];  // e[2][dz], ie[2][dz]
   // where the populations came from, for the loops of the rare paths
   const T* src;
-  int64_t pitch;
   uint32_t site;
   const SimDesc* desc;
   Where w;  // filled by locate_rare() before a rare-path loop
@@ -283,9 +288,8 @@ struct Site {
     const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
     const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
     const R W = R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0) / R(L::den());
-    const uint32_t off = sel3(w.zs, dz) + sel3(w.ys, dy) + sel3(w.xs, dx);
-    const T gv = *(const gptr<T>)((gaddr)(uintptr_t)src + (uint64_t)i * (uint64_t)pitch * sizeof(T) +
-                                   off * (uint32_t)sizeof(T));
+    const uint32_t sp = sel3(w.zs, dz) + sel3(w.ys, dy) + sel3(w.xs, dx);
+    const T gv = *(const gptr<T>)((gaddr)(uintptr_t)src + pidx<Q>(sp, i) * sizeof(T));
     const R gi = Codec<S, R>::dec(gv, W, rho_ref);
     fi = sel9(f01, dx, dy) * sel3(e2, dz);
     const R ri = sel9(r01, dx, dy) * sel3(ie2, dz);
@@ -692,18 +696,34 @@ __device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, ui
     zs[1] = (z == 0 ? nz - 1 : z - 1) * nxy;
     zs[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
   }
+  // A row of nx sites (nx a multiple of 64) is nx/64 whole blocks, i.e.
+  // nx Q contiguous elements starting at element (row start) Q.  Within the
+  // row, the source x of each lane sits at ((x / 64) Q) 64 + x % 64 plus the
+  // direction's 64 i.
+  constexpr uint32_t es = sizeof(T);
+  constexpr int Q = L::Q;
   uint32_t xo[3];
-  xo[0] = x * (uint32_t)sizeof(T);
-  xo[1] = (x == 0 ? nx - 1 : x - 1) * (uint32_t)sizeof(T);
-  xo[2] = (x == nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T);
-  const gaddr base = plane_base(src);
-  const uint64_t pb = (uint64_t)d.pitch * sizeof(T);
+  const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  xo[0] = (uint32_t)pidx<Q>(x, 0) * es;
+  xo[1] = (uint32_t)pidx<Q>(xm, 0) * es;
+  xo[2] = (uint32_t)pidx<Q>(xp, 0) * es;
+  const gaddr base = buffer_base(src);
+  const uint32_t rowbytes = nx * (uint32_t)Q * es;
+  // one descriptor per source row (c_y, c_z); direction i's run within the
+  // row's blocks is the scalar offset 64 i elements (every address stays
+  // inside the row)
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    // the descriptor starts at the source row; the range is the plane's rest
-    const uint32_t rowoff = (zs[L::dg(i, 2)] + ys[L::dg(i, 1)]) * (uint32_t)sizeof(T);
-    raw[i] = ld_buf<T>(base + i * pb + rowoff, (uint32_t)pb - rowoff, xo[L::dg(i, 0)]);
-  }
+  for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz)
+#pragma unroll
+    for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+      const __amdgpu_buffer_rsrc_t r =
+          rsrc(base + (uint64_t)(zs[dz] + ys[dy]) * Q * es, rowbytes);
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int i = dx + 3 * dy + 9 * dz;
+        raw[i] = ld_buf<T>(r, xo[dx], (uint32_t)i * kLane * es);
+      }
+    }
 }
 
 // Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
@@ -712,12 +732,11 @@ __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32
                                           T (&raw)[Lattice<D>::Q]) {
   using L = Lattice<D>;
   const Where w = locate<D>(d, s);
-  const gaddr base = plane_base(src);
-  const uint64_t pb = (uint64_t)d.pitch * sizeof(T);
+  const gaddr base = buffer_base(src);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
-    const uint32_t off = w.zs[L::dg(i, 2)] + w.ys[L::dg(i, 1)] + w.xs[L::dg(i, 0)];
-    raw[i] = ld<T>(base + i * pb, off * (uint32_t)sizeof(T));
+    const uint32_t sp = w.zs[L::dg(i, 2)] + w.ys[L::dg(i, 1)] + w.xs[L::dg(i, 0)];
+    raw[i] = *(const gptr<T>)(base + pidx<L::Q>(sp, i) * sizeof(T));
   }
 }
 
@@ -762,7 +781,6 @@ __device__ __forceinline__ void site_prepare(Site<D, S, R>& v, const SimDesc& d,
                                              const typename S::T* src, uint32_t sl, R& rho,
                                              R (&j)[3], bool equilibrium) {
   v.src = src;
-  v.pitch = d.pitch;
   v.site = sl;
   v.desc = &d;
   v.rho_ref = (R)d.rho_ref;
@@ -832,8 +850,8 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
 // collision, store of dst_i(x) at the site's own index.  `live` is false for
 // the padding lanes of the last tile: they compute on the values of site 0
 // (so that wavefront-wide votes see ordinary numbers) and store into the
-// plane padding past N, which every plane has up to the next multiple of
-// kBlock sites and which no step reads.
+// padding blocks past N, which every buffer has up to the next whole tile
+// and which no step reads.
 //
 // PHASE (closed form): kPhaseCommon leaves the lanes that need the rare
 // tier untouched and returns true for them; site_update_rare completes them.
@@ -854,7 +872,6 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
   R rho, j[3];
   site_prepare(v, d, src, sl, rho, j, MODE != kBGK);
   const R beta = (R)d.beta;
-  const int64_t pitch = d.pitch;
 
   if constexpr (MODE == kBGK) {
     // LBGK: alpha = 2 with the second-order polynomial equilibrium.
@@ -863,9 +880,8 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
     const R tb = R(2) * beta;
     R ftmin = R(INFINITY);
     uint32_t flags = 0;
-    const uint32_t so = s * es;
-    const gaddr base = plane_base(dst);
-    const uint64_t pb = (uint64_t)pitch * es;
+    const uint32_t lo = (s & 63u) * es;
+    const gaddr blk = block_base<Q>(dst, s);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R cu = R(L::c(i, 0)) * u[0] + R(L::c(i, 1)) * u[1] + R(L::c(i, 2)) * u[2];
@@ -873,7 +889,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
       const R gi = v.g(i);
       const R ft = gi + tb * (fe - gi);
       ftmin = fmin(ftmin, ft);
-      st_nt<T>(base + i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt<T>(blk + i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
     }
     if (diag & kDiagCounts) {
       if (live)
@@ -900,9 +916,8 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
     const R ab = ao.alpha * beta;
     const auto P = v.pass();
     R ftmin = R(INFINITY);
-    const uint32_t so = s * es;
-    const gaddr base = plane_base(dst);
-    const uint64_t pb = (uint64_t)pitch * es;
+    const uint32_t lo = (s & 63u) * es;
+    const gaddr blk = block_base<Q>(dst, s);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R gi = v.g(i);
@@ -911,10 +926,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
       // so f~_i = f^eq_i (1 + (1 - alpha beta) x_i) > 0.975 f^eq_i: no
       // negative population to look for.
       if constexpr (PHASE != kPhaseCommon) ftmin = fmin(ftmin, ft);
-      // a private copy of the offset per store keeps the address in the
-      // scalar-base + vector-offset form (otherwise the common offset is
-      // added first and every plane offset costs 64-bit vector arithmetic)
-      st_nt<T>(base + i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
+      st_nt<T>(blk + i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
       sched_group(i);
     }
     return SiteOut{false, record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
@@ -943,9 +955,8 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
   const AlphaOut<R> ao = choose_alpha<MODE, kPhaseRare>(v, d);
   const R ab = ao.alpha * (R)d.beta;
   R ftmin = R(INFINITY);
-  const uint32_t so = s * es;
-  const gaddr base = plane_base(dst);
-  const uint64_t pb = (uint64_t)d.pitch * es;
+  const uint32_t lo = (s & 63u) * es;
+  const gaddr blk = block_base<Q>(dst, s);
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
     R xi, fi, gi;
@@ -954,7 +965,7 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
     ftmin = fmin(ftmin, ft);
     const int nz0 = (i % 3 == 0) + (D > 1 && (i / 3) % 3 == 0) + (D > 2 && i / 9 == 0);
     const R invW = R(L::den()) / R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0);
-    st_nt<T>(base + (uint64_t)i * pb, (uint32_t)pb, so, Codec<S, R>::enc(ft, invW, v.rho_ref));
+    st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, invW, v.rho_ref));
   }
   return record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
 }

@@ -45,7 +45,7 @@ class Config(C.Structure):
                 ("storage", C.c_int32), ("alpha_fp64", C.c_int32),
                 ("secant_iters", C.c_int32), ("rho_ref", C.c_double),
                 ("root_tol", C.c_double), ("root_max_iter", C.c_int32),
-                ("diag", C.c_uint32), ("plane_pad", C.c_int32), ("reserved", C.c_int32)]
+                ("diag", C.c_uint32), ("reserved", C.c_int32 * 2)]
 
 
 class Stats(C.Structure):
@@ -135,7 +135,7 @@ def _check(rc: int):
 
 def make_config(lattice, nx, ny=1, nz=1, *, beta=0.95, mode="closed", storage="f32",
                 fp64=True, secant_iters=3, rho_ref=1.0, root_tol=1e-13,
-                root_max_iter=200, diag=0, plane_pad=-1) -> Config:
+                root_max_iter=200, diag=0) -> Config:
     cfg = Config()
     lat = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     _check(lib().elbm_config_default(C.byref(cfg), lat, nx, ny, nz))
@@ -148,7 +148,6 @@ def make_config(lattice, nx, ny=1, nz=1, *, beta=0.95, mode="closed", storage="f
     cfg.root_tol = float(root_tol)
     cfg.root_max_iter = int(root_max_iter)
     cfg.diag = int(diag)
-    cfg.plane_pad = int(plane_pad)
     return cfg
 
 

@@ -82,12 +82,20 @@ def test_server_mix_equals_alone(gpu):
         assert np.array_equal(outs[k][1].cpu().numpy(), u0), k
 
 
+def elbm_state(gpu, r):
+    cfg = gpu.make_config("d2q9", r["n"], r["n"], 1, storage=r["storage"], beta=r["beta"])
+    return (gpu.state_bytes(cfg) + 255) // 256 * 256
+
+
 def test_server_admission_small_pool(gpu):
     """A pool that fits one request at a time: requests run one after
     another in arrival order; one that can never fit is rejected."""
     reqs = [dict(k=k, n=n, steps=s, storage="f32", beta=0.99, arrival=0.0)
-            for k, (n, s) in enumerate([(128, 40), (96, 30), (128, 20), (64, 50)])]
+            for k, (n, s) in enumerate([(128, 40), (120, 30), (128, 20), (112, 50)])]
     pool = max(serving.footprint(r) for r in reqs) + 4096
+    # no request fits beside the resident state of another
+    state = {r["n"]: elbm_state(gpu, r) for r in reqs}
+    assert all(state[a["n"]] + serving.footprint(b) > pool for a in reqs for b in reqs)
     stream = torch.cuda.Stream()
     with gpu.Server(pool, max_active=8, round_steps=16, stream=stream) as srv:
         big = Wk.shear_layer(512)
