@@ -579,9 +579,12 @@ struct Acc {
     rho = j[0] = j[1] = j[2] = H = 0.0;
   }
   // wavefront counts of the count predicates; all lanes must be active
+  // (MASK: the bits that can be set; the others are not counted)
+  template <uint32_t MASK = (1u << kCntIters) - 1u>
   __device__ __forceinline__ void count_flags(uint32_t flags) {
 #pragma unroll
-    for (int k = 0; k < kCntIters; ++k) c[k] += (uint32_t)__popcll(__ballot((flags >> k) & 1u));
+    for (int k = 0; k < kCntIters; ++k)
+      if (MASK & (1u << k)) c[k] += (uint32_t)__popcll(__ballot((flags >> k) & 1u));
   }
 };
 
@@ -1021,6 +1024,11 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
     }
     uint32_t flags = 0;
     if constexpr (MODE == kClosed) {
+      // A lane the common phase completes has alpha_* = 2, no negative
+      // population (|x_i| <= 0.025) and finite values (a non-finite max|x_i|
+      // fails the tier tests and is deferred): only these counts can be set.
+      constexpr uint32_t kCommonFlags =
+          (1u << kCntAccept2) | (1u << kCntAlphaLt2) | (1u << kCntGuard);
       // the closed form in two phases: the rare tier after the common one
       bool deferred[ELBM_TILES];
 #pragma unroll
@@ -1034,10 +1042,12 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
           flags = o.flags;
         }
         if (ELBM_TILES > 1 && (diag & kDiagCounts)) {
-          acc.count_flags(flags);
+          acc.count_flags<kCommonFlags>(flags);
           flags = 0;
         }
       }
+      if (ELBM_TILES == 1 && (diag & kDiagCounts)) acc.count_flags<kCommonFlags>(flags);
+      flags = 0;
 #pragma unroll
       for (int k = 0; k < ELBM_TILES; ++k) {
         if (__any(deferred[k])) {
@@ -1060,8 +1070,8 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
           flags = 0;
         }
       }
+      if (ELBM_TILES == 1 && (diag & kDiagCounts)) acc.count_flags(flags);
     }
-    if (diag & kDiagCounts) acc.count_flags(flags);
   } else if (!(diag & kDiagCounts)) {
     return;  // padding workgroup
   }
