@@ -68,7 +68,7 @@ __global__ void k_scatter(const BoxDesc b, typename S::T* __restrict__ buf,
     eq.build(u);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      fv[i] = rho0[s] * (eq.e[0][L::dg(i, 0)] * eq.e[1][L::dg(i, 1)]) * eq.e[2][L::dg(i, 2)];
+      fv[i] = rho0[s] * (eq.e(0, L::dg(i, 0)) * eq.e(1, L::dg(i, 1))) * eq.e(2, L::dg(i, 2));
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) fv[i] = f[i * b.N + s];

@@ -164,39 +164,49 @@ __device__ __forceinline__ R sqrt_n(R y) {
 // With tensor-product weights it factorises per axis a:
 //   s_a = sqrt(1 + 3 u_a^2), A_a = 2 - s_a, z_a = (2 u_a + s_a) / (1 - u_a),
 //   f_i^eq = rho prod_a w(c_ia) A_a z_a^(c_ia),        |u_a| < 1.
-// e[a][d] holds w(c) A_a z_a^c for digit d of c, ie[a][d] its reciprocal, so
-// f^eq and 1/f^eq cost one product chain per direction and one division per
-// axis.
+// E[a][d] holds the unweighted factor A_a z_a^c for digit d of c and IE[a][d]
+// its reciprocal; with nu = 2 u + s, de = 1 - u and r = 1 / (A nu de) all six
+// follow from one reciprocal:
+//   A z = (A nu)^2 r,  A / z = (A de)^2 r,  1/A = nu de r,
+//   1/(A z) = de^2 r,  z / A = nu^2 r.
+// The weights w(0) = 2/3, w(+-1) = 1/6 are applied by the users (weight()).
 template <class R, int D>
 struct Equilibrium {
-  R e[3][3];
-  R ie[3][3];
-  R lnA[3], lnz[3];  // only filled by the entropy diagnostic
+  R E[3][3];
+  R IE[3][3];
+
+  __host__ __device__ static constexpr double weight(int d) { return d == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
 
   __device__ __forceinline__ void build(const R u[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (a < D) {
         const R ua = u[a];
-        const R s = sqrt_n<R>(R(1) + R(3) * ua * ua);
+        const R s = sqrt_n<R>(fma(R(3) * ua, ua, R(1)));
         const R A = R(2) - s;
-        const R nu = R(2) * ua + s;  // z = nu / de
+        const R nu = fma(R(2), ua, s);
         const R de = R(1) - ua;
-        const R r = rcp_n<R>(nu * de * A);
-        const R zp = nu * nu * A * r;  // z
-        const R zm = de * de * A * r;  // 1/z
-        const R iA = nu * de * r;      // 1/A
-        e[a][0] = A * R(2.0 / 3.0);
-        e[a][1] = A * zp * R(1.0 / 6.0);
-        e[a][2] = A * zm * R(1.0 / 6.0);
-        ie[a][0] = iA * R(1.5);
-        ie[a][1] = iA * zm * R(6);
-        ie[a][2] = iA * zp * R(6);
+        const R P = A * nu, M = A * de, Z = nu * de;
+        const R r = rcp_n<R>(A * Z);
+        E[a][0] = A;
+        E[a][1] = P * (P * r);
+        E[a][2] = M * (M * r);
+        IE[a][0] = Z * r;
+        IE[a][1] = de * (de * r);
+        IE[a][2] = nu * (nu * r);
       } else {
-        e[a][0] = e[a][1] = e[a][2] = R(1);
-        ie[a][0] = ie[a][1] = ie[a][2] = R(1);
+        // absent axes are never read (e() and ie() return 1 for them)
+        E[a][0] = E[a][1] = E[a][2] = R(1);
+        IE[a][0] = IE[a][1] = IE[a][2] = R(1);
       }
     }
+  }
+  // weighted factors w(d) E and their reciprocals
+  __device__ __forceinline__ R e(int a, int d) const {
+    return a < D ? R(weight(d)) * E[a][d] : R(1);
+  }
+  __device__ __forceinline__ R ie(int a, int d) const {
+    return a < D ? IE[a][d] * R(1.0 / weight(d)) : R(1);
   }
 };
 

@@ -266,17 +266,29 @@ struct Site {
   // The x- and y-axis factors are folded with rho into f01 / r01 and not
   // kept, which saves 12 doubles of registers over the whole update.
   __device__ __forceinline__ void fold(const Equilibrium<R, D>& eq) {
+    using EQ = Equilibrium<R, D>;
+    // rho and the weights enter the x- and y-axis factors once each
+    const R rw0 = rho * R(EQ::weight(0)), rw1 = rho * R(EQ::weight(1));
+    const R iw0 = irho * R(1.0 / EQ::weight(0)), iw1 = irho * R(1.0 / EQ::weight(1));
+    R x0[3], y0[3], ix0[3], iy0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      x0[d] = (d == 0 ? rw0 : rw1) * eq.E[0][d];
+      ix0[d] = (d == 0 ? iw0 : iw1) * eq.IE[0][d];
+      y0[d] = D > 1 ? R(EQ::weight(d)) * eq.E[1][d] : R(1);
+      iy0[d] = D > 1 ? eq.IE[1][d] * R(1.0 / EQ::weight(d)) : R(1);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        f01[a][b] = rho * (eq.e[0][a] * eq.e[1][b]);
-        r01[a][b] = irho * (eq.ie[0][a] * eq.ie[1][b]);
+        f01[a][b] = x0[a] * y0[b];
+        r01[a][b] = ix0[a] * iy0[b];
       }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      e2[k] = eq.e[2][k];
-      ie2[k] = eq.ie[2][k];
+      e2[k] = eq.e(2, k);
+      ie2[k] = eq.ie(2, k);
     }
   }
 
@@ -748,33 +760,41 @@ __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32
 // x-momentum term.
 template <int D, class S, class R>
 __device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (&j)[3]) {
-  rho = R(0);
-  j[0] = j[1] = j[2] = R(0);
+  constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
   R rs[3][3], rx[3][3];
 #pragma unroll
-  for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz)
+  for (int dz = 0; dz < NZ; ++dz)
 #pragma unroll
-    for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
+    for (int dy = 0; dy < NY; ++dy) {
       const int i0 = 9 * dz + 3 * dy;
       const R g0 = v.g(i0), gp = v.g(i0 + 1), gm = v.g(i0 + 2);
       rs[dy][dz] = g0 + (gp + gm);
       rx[dy][dz] = gp - gm;
     }
+  // sums start from their first term (adding to a zero is not free in IEEE
+  // arithmetic)
+  R cz[3];
+  j[0] = rx[0][0];
 #pragma unroll
-  for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) {
-    R cz = R(0);
+  for (int dz = 0; dz < NZ; ++dz) {
+    cz[dz] = rs[0][dz];
 #pragma unroll
-    for (int dy = 0; dy < (D > 1 ? 3 : 1); ++dy) {
-      cz += rs[dy][dz];
-      j[0] += rx[dy][dz];
-    }
-    rho += cz;
-    if (D > 2) j[2] += (dz == 1) ? cz : (dz == 2 ? -cz : R(0));
+    for (int dy = 1; dy < NY; ++dy) cz[dz] += rs[dy][dz];
+#pragma unroll
+    for (int dy = 0; dy < NY; ++dy)
+      if (dy + dz > 0) j[0] += rx[dy][dz];
   }
-  if (D > 1) {
+  rho = cz[0];
 #pragma unroll
-    for (int dz = 0; dz < (D > 2 ? 3 : 1); ++dz) j[1] += rs[1][dz] - rs[2][dz];
+  for (int dz = 1; dz < NZ; ++dz) rho += cz[dz];
+  j[1] = R(0);
+  j[2] = R(0);
+  if constexpr (D > 1) {
+    j[1] = rs[1][0] - rs[2][0];
+#pragma unroll
+    for (int dz = 1; dz < NZ; ++dz) j[1] += rs[1][dz] - rs[2][dz];
   }
+  if constexpr (D > 2) j[2] = cz[1] - cz[2];
 }
 
 // Loads (or takes) the site's populations, forms rho, u and, for the
