@@ -241,12 +241,15 @@ struct Site {
   __device__ __forceinline__ R g(int i) const {
     return Codec<S, R>::dec_wide(widen<R>(raw[i]), R(L::W(i)), rho_ref);
   }
-  // Each pass takes opaque copies of the z-axis factors, so that f^eq_i and
-  // 1/f^eq_i (one product each) are recomputed per pass, not kept.
+  // The z-axis factors a pass uses.  f^eq_i and 1/f^eq_i (one product
+  // each) are recomputed per pass, not kept; passes that could share such
+  // products (the middle tier with either of the others) take opaque copies
+  // (pass_opaque) so that the compiler does not keep Q products live across
+  // them.
   struct Pass {
     R e2[3], ie2[3];
   };
-  __device__ __forceinline__ Pass pass() const {
+  __device__ __forceinline__ Pass pass_opaque() const {
     Pass p;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -255,6 +258,19 @@ struct Site {
     }
     return p;
   }
+  __device__ __forceinline__ Pass pass() const {
+    // with FP64 storage every pass takes opaque copies (the register file
+    // has no room for shared products next to Q FP64 populations)
+    if constexpr (sizeof(T) == 8) return pass_opaque();
+    Pass p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      p.e2[k] = e2[k];
+      p.ie2[k] = ie2[k];
+    }
+    return p;
+  }
+
   __device__ __forceinline__ R fe(int i, const Pass& p) const {
     const R q = f01[L::dg(i, 0)][L::dg(i, 1)];
     return D > 2 ? q * p.e2[L::dg(i, 2)] : q;
@@ -409,13 +425,33 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   if constexpr (PHASE != kPhaseRare) {
   const SeriesK<R, Base<R>::K> ser;
   const auto P = v.pass();
+  if constexpr (D == 3) {
+    // f^eq_i = f01[dx][dy] e2[dz]: the sums over dz are formed with e2
+    // alone and multiplied by f01 once per (dx, dy)
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const R xi = v.x(i, P);
-    if (kXmax) xmax = fmax(xmax, xi);
-    xabs = fmax(xabs, fabs(xi));
-    ser.accum(xi, v.fe(i, P), sE, sO);
-    sched_group(i);
+    for (int dxy = 0; dxy < 9; ++dxy) {
+      R iE = R(0), iO = R(0);
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        const int i = dxy + 9 * dz;
+        const R xi = v.x(i, P);
+        if (kXmax) xmax = fmax(xmax, xi);
+        xabs = fmax(xabs, fabs(xi));
+        ser.accum(xi, P.e2[dz], iE, iO);
+      }
+      sE = fma(v.f01[dxy % 3][dxy / 3], iE, sE);
+      sO = fma(v.f01[dxy % 3][dxy / 3], iO, sO);
+      sched_group(dxy);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R xi = v.x(i, P);
+      if (kXmax) xmax = fmax(xmax, xi);
+      xabs = fmax(xabs, fabs(xi));
+      ser.accum(xi, v.fe(i, P), sE, sO);
+      sched_group(i);
+    }
   }
   }
   if constexpr (PHASE != kPhaseRare) {
@@ -452,7 +488,7 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   if (PHASE != kPhaseRare && __any(mid)) {
     R mE = R(0), mO = R(0);
     const SeriesK<R, Base<R>::KM> ser;
-    const auto P = v.pass();
+    const auto P = v.pass_opaque();
 #pragma unroll
     for (int i = 0; i < Q; ++i) ser.accum(v.x(i, P), v.fe(i, P), mE, mO);
     R cE, cO;
