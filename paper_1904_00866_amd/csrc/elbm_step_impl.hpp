@@ -38,6 +38,14 @@ __device__ __forceinline__ R opaque(R v) {
   return v;
 }
 
+// Wave priority while a wave issues its loads.  A wave that starts raises
+// its priority until its Q loads are issued, so the instruction arbiter
+// issues them ahead of the arithmetic of the waves already computing: the
+// loads of the next tiles then overlap that arithmetic instead of waiting
+// behind it (512^3 D3Q27 closed form: 5.26 -> 5.07 ms per step).
+#ifndef ELBM_LOAD_PRIO
+#define ELBM_LOAD_PRIO 2
+#endif
 // Scheduling fence every ELBM_SCHED_GROUP directions of an unrolled pass
 // (0: none): keeps the scheduler from hoisting the loads and conversions of
 // many directions at once, which would hold their registers live.
@@ -1070,6 +1078,9 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
   acc.init();
   if (unit * ELBM_TILES * kBlock < N) {
     T raw[ELBM_TILES][Q];
+#if ELBM_LOAD_PRIO
+    __builtin_amdgcn_s_setprio(ELBM_LOAD_PRIO);
+#endif
 #pragma unroll
     for (int k = 0; k < ELBM_TILES; ++k) {
       const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
@@ -1078,6 +1089,10 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
       else
         load_site<D>(d, src, s < N ? s : 0u, raw[k]);
     }
+#if ELBM_LOAD_PRIO
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_setprio(0);
+#endif
     uint32_t flags = 0;
     if constexpr (MODE == kClosed) {
       // A lane the common phase completes has alpha_* = 2, no negative
