@@ -194,6 +194,29 @@ int64_t elbm_time(const elbm_sim *sim);
  * handle's pending work first. */
 elbm_status elbm_destroy(elbm_sim *sim);
 
+/* ---- checkpoint / resume ------------------------------------------------
+ * A checkpoint is the current populations bit for bit in their stored form
+ * (an opaque blob of elbm_checkpoint_bytes() bytes) plus the time t.  The
+ * step is a function of the stored populations only, so a simulation
+ * restored from a checkpoint continues exactly as the original would
+ * (bitwise).  A checkpoint is valid for simulations of the same lattice,
+ * box and storage (other configuration fields may differ, e.g. beta or the
+ * alpha mode). */
+
+/* Bytes of a checkpoint (0 and ELBM_EINVAL for a NULL handle). */
+size_t elbm_checkpoint_bytes(const elbm_sim *sim);
+
+/* Copy the current populations into dst (device, >= bytes of
+ * elbm_checkpoint_bytes) on the simulation's stream; *t (host) receives the
+ * time of the state.  Asynchronous like elbm_step. */
+elbm_status elbm_export(elbm_sim *sim, void *dst, size_t bytes, int64_t *t);
+
+/* Replace the current populations with a checkpoint src (device, bytes ==
+ * elbm_checkpoint_bytes) taken from a simulation of the same lattice, box
+ * and storage, and set the time to t.  Asynchronous; the alpha field and
+ * the diagnostics of the previous step are invalidated. */
+elbm_status elbm_import(elbm_sim *sim, const void *src, size_t bytes, int64_t t);
+
 /* Message of the calling thread's last error ("" if none). */
 const char *elbm_last_error(void);
 

@@ -513,6 +513,45 @@ elbm_status elbm_destroy(elbm_sim* s) {
   return st;
 }
 
+size_t elbm_checkpoint_bytes(const elbm_sim* s) {
+  if (!s) {
+    fail(ELBM_EINVAL, "simulation handle is NULL");
+    return 0;
+  }
+  return size_t(s->L.Q) * size_t(s->L.padded) * size_t(s->L.esize);
+}
+
+elbm_status elbm_export(elbm_sim* s, void* dst, size_t bytes, int64_t* t) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  const size_t n = elbm_checkpoint_bytes(s);
+  if (!dst || !t) return fail(ELBM_EINVAL, "dst / t is NULL");
+  if (bytes < n) return fail(ELBM_ENOMEM, "checkpoint buffer of %zu bytes, %zu needed", bytes, n);
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  const hipError_t e = hipMemcpyAsync(dst, s->buf[s->cur], n, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "elbm_export");
+  *t = s->t;
+  return ELBM_OK;
+}
+
+elbm_status elbm_import(elbm_sim* s, const void* src, size_t bytes, int64_t t) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  const size_t n = elbm_checkpoint_bytes(s);
+  if (!src) return fail(ELBM_EINVAL, "src is NULL");
+  if (bytes != n)
+    return fail(ELBM_EINVAL, "checkpoint of %zu bytes, this simulation's is %zu", bytes, n);
+  if (t < 0) return fail(ELBM_EINVAL, "t < 0");
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  const hipError_t e = hipMemcpyAsync(s->buf[s->cur], src, n, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "elbm_import");
+  s->t = t;
+  s->have_alpha = s->have_stats = false;
+  return ELBM_OK;
+}
+
 const char* elbm_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"

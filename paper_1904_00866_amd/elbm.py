@@ -29,7 +29,8 @@ EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_pop
            "elbm_alpha_field", "elbm_stats", "elbm_time", "elbm_destroy",
            "elbm_last_error", "elbm_step_batch", "elbm_server_create", "elbm_server_submit",
            "elbm_server_poll", "elbm_server_wait", "elbm_server_sim", "elbm_server_release",
-           "elbm_server_get_stats", "elbm_server_destroy"]
+           "elbm_server_get_stats", "elbm_server_destroy", "elbm_checkpoint_bytes",
+           "elbm_export", "elbm_import"]
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
@@ -119,6 +120,10 @@ def lib():
         L.elbm_server_release.argtypes = [vp, C.c_int64]
         L.elbm_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.elbm_server_destroy.argtypes = [vp]
+        L.elbm_checkpoint_bytes.argtypes = [vp]
+        L.elbm_checkpoint_bytes.restype = C.c_size_t
+        L.elbm_export.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_int64)]
+        L.elbm_import.argtypes = [vp, vp, C.c_size_t, C.c_int64]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.elbm_state_bytes.restype = C.c_size_t
@@ -247,6 +252,20 @@ class Simulation:
         a = torch.empty(self.N, dtype=torch.float64, device=self.device)
         _check(lib().elbm_alpha_field(self.handle, _ptr(a)))
         return a
+
+    def export(self):
+        """Checkpoint: (device uint8 tensor of the stored populations, t)."""
+        n = lib().elbm_checkpoint_bytes(self.handle)
+        with torch.cuda.stream(self.stream):
+            blob = torch.empty(n, dtype=torch.uint8, device=self.device)
+        t = C.c_int64()
+        _check(lib().elbm_export(self.handle, _ptr(blob), n, C.byref(t)))
+        return blob, t.value
+
+    def import_(self, blob: torch.Tensor, t: int):
+        """Resume from a checkpoint of a simulation with the same lattice,
+        box and storage."""
+        _check(lib().elbm_import(self.handle, _ptr(blob), blob.numel(), int(t)))
 
     def stats(self) -> dict:
         s = Stats()

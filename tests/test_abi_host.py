@@ -118,6 +118,10 @@ def test_init_argument_errors_before_device_work():
     assert L.elbm_step(None, 1) == -1
     assert L.elbm_destroy(None) == 0
     assert L.elbm_time(None) == -1
+    assert L.elbm_checkpoint_bytes(None) == 0
+    t = C.c_int64()
+    assert L.elbm_export(None, None, 0, C.byref(t)) == -1
+    assert L.elbm_import(None, None, 0, 0) == -1
 
 
 def test_batch_argument_errors():

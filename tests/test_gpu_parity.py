@@ -169,6 +169,37 @@ def test_one_step_reduced_storage(gpu, orc, D, storage):
     sim.close()
 
 
+ROW_SHAPES = {1: (192, 1, 1), 2: (128, 6, 1), 3: (64, 5, 3)}  # nx % 64 == 0, ragged N
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f32dev", "f16dev"])
+@pytest.mark.parametrize("mode", ["closed", "bgk"])
+def test_one_step_row_aligned_boxes(gpu, orc, D, storage, mode):
+    """Boxes whose x-rows hold whole 64-site blocks take the kernel's
+    row-descriptor loads: one step against the oracle from the decoded
+    stored state, to 1e-13 (FP64) or one output rounding."""
+    shape = ROW_SHAPES[D]
+    N = int(np.prod(shape))
+    f0 = _random_state(D, N, seed=700 + 10 * D + len(storage) + len(mode), eps=0.02, tilt=0.05)
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.97, mode=mode)
+    fq = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    fo, _, _ = orc.step(_ocfg(orc, D, shape, beta=0.97, mode=mode), fq)
+    W = H.textbook_weights(D)[:, None]
+    if storage == "f64":
+        tol = 1e-13 * np.abs(fo)
+    elif storage == "f32":
+        tol = 2.0 ** -24 * np.abs(fo) * 1.01 + 1e-300
+    elif storage == "f32dev":
+        tol = W * (2.0 ** -24 * np.abs(fo / W - 1.0) * 1.01 + 1e-12)
+    else:
+        tol = W * (2.0 ** -11 * np.abs(fo / W - 1.0) * 1.01 + 2.0 ** -24)
+    assert np.all(np.abs(fg - fo) <= tol)
+    sim.close()
+
+
 def test_fp32_arithmetic_ablation(gpu, orc):
     """All-FP32 site arithmetic (closed form): one step within 2e-6 relative."""
     shape = SHAPES[2]
@@ -309,3 +340,32 @@ def test_shock_tube_d1q3_alpha_field(gpu, orc):
     dev = np.abs(2.0 - ag[split + 1:]).max() / 2.0 * 100.0
     assert abs(dev - 3.96) < 0.5
     sim.close()
+
+
+@pytest.mark.parametrize("D,shape,storage", [(2, (64, 40, 1), "f16dev"), (3, (20, 12, 9), "f32"),
+                                             (3, (64, 4, 4), "f32dev"), (2, (37, 23, 1), "f64")])
+def test_checkpoint_resume_is_bitwise(gpu, D, shape, storage):
+    """A simulation restored from a checkpoint continues bit for bit as the
+    original (the step depends on the stored populations only)."""
+    N = int(np.prod(shape))
+    rho, u = Wk.random_velocity_field(D, N, 0.08, seed=N + D)
+    kw = dict(storage=storage, beta=0.985, diag=gpu.DIAG_ALPHA)
+    a = _sim(gpu, D, shape, rho=rho, u=u, **kw)
+    a.step(25)
+    blob, t = a.export()
+    a.step(35)
+    fa, aa = a.populations().cpu().numpy(), a.alpha_field().cpu().numpy()
+    rho2, u2 = Wk.random_velocity_field(D, N, 0.02, seed=1)
+    b = _sim(gpu, D, shape, rho=rho2, u=u2, **kw)
+    b.import_(blob, t)
+    assert b.t == 25
+    with pytest.raises(gpu.ElbmError):
+        b.alpha_field()  # invalidated by the import
+    b.step(35)
+    assert b.t == 60
+    assert np.array_equal(b.populations().cpu().numpy(), fa)
+    assert np.array_equal(b.alpha_field().cpu().numpy(), aa)
+    with pytest.raises(gpu.ElbmError):
+        b.import_(blob[:-1], 0)  # wrong size
+    a.close()
+    b.close()
