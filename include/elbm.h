@@ -300,7 +300,8 @@ elbm_status elbm_server_submit(elbm_server *srv, const elbm_request *req,
 elbm_status elbm_server_poll(elbm_server *srv, int64_t id, elbm_request_info *info);
 
 /* Block until request id is done or failed, or timeout_s seconds pass
- * (ELBM_ESTATE on timeout; timeout_s < 0 waits without limit). */
+ * (ELBM_ESTATE on timeout; timeout_s < 0 waits without limit; ELBM_EDEVICE
+ * if the request failed).  Done means its final rho/u are in out_rho/out_u. */
 elbm_status elbm_server_wait(elbm_server *srv, int64_t id, double timeout_s);
 
 /* The simulation of a completed keep_state request (valid until release). */
@@ -311,7 +312,10 @@ elbm_status elbm_server_release(elbm_server *srv, int64_t id);
 
 elbm_status elbm_server_get_stats(elbm_server *srv, elbm_server_stats *stats);
 
-/* Finish every submitted request, stop the scheduler, free the server. */
+/* Stop accepting requests, finish every request that can still be admitted,
+ * stop the scheduler and free the server and every kept state.  Requests
+ * left queued because kept states hold the pool end as ELBM_REQ_FAILED.
+ * The caller's pool may be freed after this returns. */
 elbm_status elbm_server_destroy(elbm_server *srv);
 
 #ifdef __cplusplus
