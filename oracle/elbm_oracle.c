@@ -20,7 +20,10 @@
  * Readings of points the paper leaves open (each one is listed with its
  * reason in the design notes of the repository):
  *   - lattice units, c_s^2 = 1/3, tensor-product weights W = (2/3,1/6,1/6)^D;
- *   - the equilibrium is written in its closed product form (derived below);
+ *   - on the tensor-product lattices the equilibrium is written in its closed
+ *     product form (derived below); on D3Q19, whose weights do not factorise,
+ *     it is the minimiser of Eq. (3) found by Newton's method on the Lagrange
+ *     multipliers (the same solver is exported for every lattice);
  *   - entropy differences between states with equal moments are evaluated
  *     as relative entropies with respect to f^eq (exact identity, below);
  *   - 0 ln 0 = 0; alpha_max = +inf when no i has f_i^eq < f_i;
@@ -42,16 +45,44 @@
 
 typedef struct {
   int D, Q;
+  int product;          /* weights factorise per axis (D1Q3, D2Q9, D3Q27)  */
   int c[QMAX][3];
   double W[QMAX];
 } lat_t;
 
-/* Direction i <-> c_i: i = d(c_x) + 3 d(c_y) + 9 d(c_z), d(0)=0, d(1)=1,
- * d(-1)=2.  W_i = prod_a w(c_ia), w(0) = 4/6, w(+-1) = 1/6, i.e.
- * W_i = 4^{#zero components} / 6^D, formed with one rounding. */
-static int make_lattice(int D, lat_t *L) {
+/* Lattice codes: 1, 2, 3 for the tensor-product lattices D1Q3, D2Q9, D3Q27,
+ * 19 for D3Q19.
+ * Direction i <-> c_i on the tensor-product lattices: i = d(c_x) + 3 d(c_y)
+ * + 9 d(c_z), d(0)=0, d(1)=1, d(-1)=2.  W_i = prod_a w(c_ia), w(0) = 4/6,
+ * w(+-1) = 1/6, i.e. W_i = 4^{#zero components} / 6^D, formed with one
+ * rounding.
+ * D3Q19 keeps the D3Q27 directions with at most two nonzero components, in
+ * the order of their D3Q27 index, with the standard weights 1/3 (rest),
+ * 1/18 (|c|^2 = 1) and 1/36 (|c|^2 = 2). */
+static int make_lattice(int code, lat_t *L) {
+  if (code == 19) {
+    L->D = 3;
+    L->Q = 0;
+    L->product = 0;
+    for (int j = 0; j < 27; ++j) {
+      int c[3], rem = j, nnz = 0;
+      for (int a = 0; a < 3; ++a) {
+        int d = rem % 3;
+        rem /= 3;
+        c[a] = (d == 0) ? 0 : (d == 1) ? 1 : -1;
+        nnz += (c[a] != 0);
+      }
+      if (nnz == 3) continue;
+      for (int a = 0; a < 3; ++a) L->c[L->Q][a] = c[a];
+      L->W[L->Q] = (nnz == 0) ? 1.0 / 3.0 : (nnz == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+      L->Q++;
+    }
+    return 0;
+  }
+  int D = code;
   if (D < 1 || D > 3) return -1;
   L->D = D;
+  L->product = 1;
   L->Q = (D == 1) ? 3 : (D == 2) ? 9 : 27;
   double den = (D == 1) ? 6.0 : (D == 2) ? 36.0 : 216.0;
   for (int i = 0; i < L->Q; ++i) {
@@ -73,6 +104,19 @@ static int make_lattice(int D, lat_t *L) {
   return 0;
 }
 
+/* u inside the domain of the entropic equilibrium: the interior of the
+ * convex hull of the velocities (the mean of c under positive weights).
+ * Tensor-product lattices: |u_a| < 1.  D3Q19 (no corner velocities): also
+ * |u_x| + |u_y| + |u_z| < 2. */
+static int u_admissible(const lat_t *L, const double *u) {
+  double s = 0.0;
+  for (int a = 0; a < L->D; ++a) {
+    if (!(fabs(u[a]) < 1.0)) return 0;
+    s += fabs(u[a]);
+  }
+  return L->product || s < 2.0;
+}
+
 /* ---- moments: rho = sum_i f_i, rho u = sum_i c_i f_i (after Eq. (3)) ---- */
 static void moments(const lat_t *L, const double *f, double *rho, double *u) {
   double r = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -92,8 +136,8 @@ static void moments(const lat_t *L, const double *f, double *rho, double *u) {
  *   u_a = (z - 1/z) / (4 + z + 1/z)        ->  z_a = (2u_a + s_a)/(1 - u_a),
  *   s_a = sqrt(1 + 3 u_a^2),  normalisation (2/3 + (z+1/z)/6)^-1 = 2 - s_a,
  * hence f_i^eq = rho W_i prod_a (2 - s_a) z_a^{c_ia}, defined for |u_a| < 1. */
-static void equilibrium(const lat_t *L, double rho, const double *u,
-                        double *feq) {
+static void equilibrium_product(const lat_t *L, double rho, const double *u,
+                                double *feq) {
   double A[3] = {1.0, 1.0, 1.0}, z[3] = {1.0, 1.0, 1.0};
   for (int a = 0; a < L->D; ++a) {
     double s = sqrt(1.0 + 3.0 * u[a] * u[a]);
@@ -108,6 +152,122 @@ static void equilibrium(const lat_t *L, double rho, const double *u,
     }
     feq[i] = v;
   }
+}
+
+/* The same minimiser for any velocity set, without a closed form.  With
+ * p_i(l) = W_i exp(l.c_i) / Z(l), Z(l) = sum_i W_i exp(l.c_i), the
+ * constraints read m(l) := sum_i c_i p_i(l) = u, and m(l) - u is the gradient
+ * of the convex function F(l) = ln Z(l) - l.u, whose Hessian is the
+ * covariance sum_i c_i c_i^T p_i - m m^T.  Newton's method on F from l = 0,
+ * with step halving while a long step fails to decrease F; it stops after a
+ * step below 1e-12 (quadratic convergence leaves an error of order its
+ * square).  Then f_i^eq = rho p_i(l).  Returns the iteration count, or -1 if
+ * it did not converge (feq is then NaN). */
+static void F_of(const lat_t *L, const double *u, const double *l, double *F,
+                 double *g, double H[3][3]) {
+  double Z = 0.0, m[3] = {0.0, 0.0, 0.0}, S[3][3] = {{0.0}};
+  for (int i = 0; i < L->Q; ++i) {
+    double lc = 0.0;
+    for (int a = 0; a < L->D; ++a) lc += l[a] * L->c[i][a];
+    double p = L->W[i] * exp(lc);
+    Z += p;
+    for (int a = 0; a < L->D; ++a) {
+      m[a] += L->c[i][a] * p;
+      for (int b = 0; b < L->D; ++b) S[a][b] += L->c[i][a] * L->c[i][b] * p;
+    }
+  }
+  double lu = 0.0;
+  for (int a = 0; a < L->D; ++a) lu += l[a] * u[a];
+  *F = log(Z) - lu;
+  if (g)
+    for (int a = 0; a < L->D; ++a) {
+      g[a] = m[a] / Z - u[a];
+      for (int b = 0; b < L->D; ++b) H[a][b] = S[a][b] / Z - (m[a] / Z) * (m[b] / Z);
+    }
+}
+
+/* Solve A x = r (n <= 3) by Gaussian elimination with partial pivoting. */
+static int solve_small(int n, double A[3][3], double *r, double *x) {
+  double M[3][4];
+  for (int a = 0; a < n; ++a) {
+    for (int b = 0; b < n; ++b) M[a][b] = A[a][b];
+    M[a][n] = r[a];
+  }
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int a = k + 1; a < n; ++a)
+      if (fabs(M[a][k]) > fabs(M[piv][k])) piv = a;
+    if (M[piv][k] == 0.0) return -1;
+    for (int b = 0; b <= n; ++b) {
+      double t = M[k][b];
+      M[k][b] = M[piv][b];
+      M[piv][b] = t;
+    }
+    for (int a = k + 1; a < n; ++a) {
+      double f = M[a][k] / M[k][k];
+      for (int b = k; b <= n; ++b) M[a][b] -= f * M[k][b];
+    }
+  }
+  for (int a = n - 1; a >= 0; --a) {
+    double v = M[a][n];
+    for (int b = a + 1; b < n; ++b) v -= M[a][b] * x[b];
+    x[a] = v / M[a][a];
+  }
+  return 0;
+}
+
+static int equilibrium_minimiser(const lat_t *L, double rho, const double *u,
+                                 double *feq) {
+  const int D = L->D;
+  double l[3] = {0.0, 0.0, 0.0};
+  int iters = -1;
+  for (int it = 1; it <= 60; ++it) {
+    double F, g[3], H[3][3], d[3], ng[3];
+    F_of(L, u, l, &F, g, H);
+    for (int a = 0; a < D; ++a) ng[a] = -g[a];
+    if (solve_small(D, H, ng, d)) break;
+    double dmax = 0.0, slope = 0.0;
+    for (int a = 0; a < D; ++a) {
+      if (fabs(d[a]) > dmax) dmax = fabs(d[a]);
+      slope += g[a] * d[a];
+    }
+    double t = 1.0;
+    if (dmax > 1e-6) {
+      /* a long step: halve it until F decreases enough (Armijo) */
+      for (int k = 0; k < 40; ++k) {
+        double lt[3], Ft;
+        for (int a = 0; a < D; ++a) lt[a] = l[a] + t * d[a];
+        F_of(L, u, lt, &Ft, NULL, NULL);
+        if (Ft <= F + 1e-4 * t * slope) break;
+        t *= 0.5;
+      }
+    }
+    for (int a = 0; a < D; ++a) l[a] += t * d[a];
+    if (t * dmax <= 1e-12) {
+      iters = it;
+      break;
+    }
+  }
+  if (iters < 0) {
+    for (int i = 0; i < L->Q; ++i) feq[i] = NAN;
+    return -1;
+  }
+  double Z = 0.0, p[QMAX];
+  for (int i = 0; i < L->Q; ++i) {
+    double lc = 0.0;
+    for (int a = 0; a < D; ++a) lc += l[a] * L->c[i][a];
+    p[i] = L->W[i] * exp(lc);
+    Z += p[i];
+  }
+  for (int i = 0; i < L->Q; ++i) feq[i] = rho * (p[i] / Z);
+  return iters;
+}
+
+/* f^eq by the closed product form where the weights factorise, else by the
+ * minimiser. */
+static void equilibrium(const lat_t *L, double rho, const double *u, double *feq) {
+  if (L->product) equilibrium_product(L, rho, u, feq);
+  else (void)equilibrium_minimiser(L, rho, u, feq);
 }
 
 /* Polynomial (second-order) equilibrium of LBGK, the alpha = 2 special case
@@ -305,10 +465,10 @@ static double choose_alpha(const lat_t *L, const orc_params *p, const double *f,
 
 static int check_params(const orc_params *p, lat_t *L) {
   if (!p) return -1;
-  if (make_lattice(p->D, L)) return -1;
+  if (make_lattice(p->lattice, L)) return -1;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
-  if (p->D == 1 && (p->ny != 1 || p->nz != 1)) return -1;
-  if (p->D == 2 && p->nz != 1) return -1;
+  if (L->D == 1 && (p->ny != 1 || p->nz != 1)) return -1;
+  if (L->D == 2 && p->nz != 1) return -1;
   if (!(p->beta > 0.0 && p->beta < 1.0)) return -1;
   if (p->mode < ORC_ALPHA_CLOSED || p->mode > ORC_ALPHA_SECANT) return -1;
   if (p->mode == ORC_ALPHA_SECANT && p->secant_iters < 1) return -1;
@@ -346,9 +506,9 @@ static void collide(const lat_t *L, const orc_params *p, const double *f,
 }
 
 /* ---- exported single-state functions ------------------------------------ */
-int orc_lattice(int32_t D, int32_t *Q, int32_t *c, double *W) {
+int orc_lattice(int32_t lattice, int32_t *Q, int32_t *c, double *W) {
   lat_t L;
-  if (make_lattice(D, &L)) return -1;
+  if (make_lattice(lattice, &L)) return -1;
   if (Q) *Q = L.Q;
   for (int i = 0; i < L.Q; ++i) {
     if (c)
@@ -358,52 +518,64 @@ int orc_lattice(int32_t D, int32_t *Q, int32_t *c, double *W) {
   return 0;
 }
 
-int orc_equilibrium(int32_t D, double rho, const double *u, double *feq) {
+int orc_equilibrium(int32_t lattice, double rho, const double *u, double *feq) {
   lat_t L;
-  if (make_lattice(D, &L) || !(rho > 0.0)) return -1;
-  for (int a = 0; a < D; ++a)
-    if (!(fabs(u[a]) < 1.0)) return -1;
-  equilibrium(&L, rho, u, feq);
+  if (make_lattice(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
+  double v[QMAX];
+  equilibrium(&L, rho, u, v);
+  for (int i = 0; i < L.Q; ++i) {
+    if (isnan(v[i])) return -1;
+    feq[i] = v[i];
+  }
   return 0;
 }
 
-int orc_equilibrium_poly(int32_t D, double rho, const double *u, double *feq) {
+int orc_equilibrium_minimiser(int32_t lattice, double rho, const double *u,
+                              double *feq, int32_t *iters) {
   lat_t L;
-  if (make_lattice(D, &L)) return -1;
+  if (make_lattice(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
+  int it = equilibrium_minimiser(&L, rho, u, feq);
+  if (iters) *iters = it;
+  return it < 0 ? -1 : 0;
+}
+
+int orc_equilibrium_poly(int32_t lattice, double rho, const double *u, double *feq) {
+  lat_t L;
+  if (make_lattice(lattice, &L)) return -1;
   equilibrium_poly(&L, rho, u, feq);
   return 0;
 }
 
-int orc_moments_site(int32_t D, const double *f, double *rho, double *u) {
+int orc_moments_site(int32_t lattice, const double *f, double *rho, double *u) {
   lat_t L;
-  if (make_lattice(D, &L)) return -1;
+  if (make_lattice(lattice, &L)) return -1;
   moments(&L, f, rho, u);
   return 0;
 }
 
-double orc_entropy(int32_t D, const double *f) {
+double orc_entropy(int32_t lattice, const double *f) {
   lat_t L;
-  if (make_lattice(D, &L)) return NAN;
+  if (make_lattice(lattice, &L)) return NAN;
   return entropy(&L, f);
 }
 
-double orc_entropy_rel(int32_t D, const double *g, const double *feq) {
+double orc_entropy_rel(int32_t lattice, const double *g, const double *feq) {
   lat_t L;
-  if (make_lattice(D, &L)) return NAN;
+  if (make_lattice(lattice, &L)) return NAN;
   double x[QMAX];
   deviations(&L, g, feq, x);
   return Hrel_of(&L, feq, x, 0.0);
 }
 
-double orc_alpha_max(int32_t D, const double *f, const double *feq) {
+double orc_alpha_max(int32_t lattice, const double *f, const double *feq) {
   lat_t L;
-  if (make_lattice(D, &L)) return NAN;
+  if (make_lattice(lattice, &L)) return NAN;
   return alpha_max_of(&L, f, feq);
 }
 
-double orc_G(int32_t D, const double *f, double alpha) {
+double orc_G(int32_t lattice, const double *f, double alpha) {
   lat_t L;
-  if (make_lattice(D, &L)) return NAN;
+  if (make_lattice(lattice, &L)) return NAN;
   double rho, u[3], feq[QMAX], x[QMAX];
   moments(&L, f, &rho, u);
   equilibrium(&L, rho, u, feq);
@@ -440,11 +612,10 @@ int orc_init(const orc_params *p, const double *rho0, const double *u0,
   for (int64_t s = 0; s < N; ++s) {
     double u[3] = {0.0, 0.0, 0.0}, feq[QMAX];
     if (!(rho0[s] > 0.0)) return -2;
-    for (int a = 0; a < L.D; ++a) {
-      u[a] = u0[a * N + s];
-      if (!(fabs(u[a]) < 1.0)) return -2;
-    }
+    for (int a = 0; a < L.D; ++a) u[a] = u0[a * N + s];
+    if (!u_admissible(&L, u)) return -2;
     equilibrium(&L, rho0[s], u, feq);
+    if (isnan(feq[0])) return -2;
     for (int i = 0; i < L.Q; ++i) f[i * N + s] = feq[i];
   }
   return 0;

@@ -11,10 +11,14 @@
  *
  * Conventions (the same ones the C-ABI library documents):
  *   - lattice units, delta_x = delta_t = 1, c_s^2 = 1/3;
- *   - D in {1,2,3}; Q = 3^D; c_i in {-1,0,1}^D with the index
- *     i = d(c_x) + 3 d(c_y) + 9 d(c_z), d(0)=0, d(+1)=1, d(-1)=2;
- *   - weights W_i = prod_a w(c_ia), w(0)=2/3, w(+-1)=1/6
+ *   - lattice codes 1, 2, 3: the tensor-product lattices D1Q3, D2Q9, D3Q27,
+ *     Q = 3^D, c_i in {-1,0,1}^D with the index
+ *     i = d(c_x) + 3 d(c_y) + 9 d(c_z), d(0)=0, d(+1)=1, d(-1)=2, and
+ *     weights W_i = prod_a w(c_ia), w(0)=2/3, w(+-1)=1/6
  *     (D1Q3, D2Q9: 4/9,1/9,1/36, D3Q27: 8/27,2/27,1/54,1/216);
+ *   - lattice code 19: D3Q19, the D3Q27 directions with at most two nonzero
+ *     components in the order of their D3Q27 index, W = 1/3 (rest),
+ *     1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2);
  *   - populations are SoA: f[i*N + s], s = x + nx*(y + ny*z), x fastest;
  *     velocities are SoA: u[a*N + s].
  *
@@ -40,7 +44,7 @@ enum {
 };
 
 typedef struct {
-  int32_t D;            /* 1, 2 or 3                                          */
+  int32_t lattice;      /* lattice code: 1, 2, 3 or 19                        */
   int32_t nx, ny, nz;   /* periodic box; ny = 1 for D = 1, nz = 1 for D <= 2  */
   double beta;          /* Eq. (2), in (0,1)                                  */
   int32_t mode;         /* ORC_ALPHA_*                                        */
@@ -78,14 +82,21 @@ typedef struct {
 } orc_diag;
 
 /* ---- lattice and single-state functions -------------------------------- */
-int orc_lattice(int32_t D, int32_t *Q, int32_t *c /* Q*3 */, double *W);
-int orc_equilibrium(int32_t D, double rho, const double *u, double *feq);
-int orc_equilibrium_poly(int32_t D, double rho, const double *u, double *feq);
-int orc_moments_site(int32_t D, const double *f, double *rho, double *u);
-double orc_entropy(int32_t D, const double *f);                /* Eq. (3) */
-double orc_entropy_rel(int32_t D, const double *g, const double *feq);
-double orc_alpha_max(int32_t D, const double *f, const double *feq);
-double orc_G(int32_t D, const double *f, double alpha);        /* H(f*)-H(f) */
+/* The first argument is a lattice code; u has 3 entries (unused ones 0). */
+int orc_lattice(int32_t lattice, int32_t *Q, int32_t *c /* Q*3 */, double *W);
+/* f^eq: the closed product form (codes 1-3) or the minimiser (code 19);
+ * -1 outside the domain (rho <= 0, u outside the velocities' hull). */
+int orc_equilibrium(int32_t lattice, double rho, const double *u, double *feq);
+/* f^eq by Newton's method on the Lagrange multipliers, for any lattice;
+ * *iters = Newton iterations. */
+int orc_equilibrium_minimiser(int32_t lattice, double rho, const double *u,
+                              double *feq, int32_t *iters);
+int orc_equilibrium_poly(int32_t lattice, double rho, const double *u, double *feq);
+int orc_moments_site(int32_t lattice, const double *f, double *rho, double *u);
+double orc_entropy(int32_t lattice, const double *f);                /* Eq. (3) */
+double orc_entropy_rel(int32_t lattice, const double *g, const double *feq);
+double orc_alpha_max(int32_t lattice, const double *f, const double *feq);
+double orc_G(int32_t lattice, const double *f, double alpha);        /* H(f*)-H(f) */
 int orc_alpha(const orc_params *p, const double *f, orc_site_info *info);
 int orc_collide_site(const orc_params *p, const double *f, double *ftilde,
                      orc_site_info *info);

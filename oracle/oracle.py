@@ -21,7 +21,7 @@ MODES = {"closed": CLOSED, "newton": NEWTON, "bisect": BISECT, "bgk": BGK,
 
 
 class Params(C.Structure):
-    _fields_ = [("D", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+    _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nz", C.c_int32), ("beta", C.c_double), ("mode", C.c_int32),
                 ("secant_iters", C.c_int32), ("root_tol", C.c_double),
                 ("root_max_iter", C.c_int32), ("nthreads", C.c_int32)]
@@ -59,6 +59,7 @@ def lib():
         ip = C.POINTER(C.c_int32)
         L.orc_lattice.argtypes = [C.c_int32, ip, ip, dp]
         L.orc_equilibrium.argtypes = [C.c_int32, C.c_double, dp, dp]
+        L.orc_equilibrium_minimiser.argtypes = [C.c_int32, C.c_double, dp, dp, ip]
         L.orc_equilibrium_poly.argtypes = [C.c_int32, C.c_double, dp, dp]
         L.orc_moments_site.argtypes = [C.c_int32, dp, dp, dp]
         L.orc_entropy.argtypes = [C.c_int32, dp]
@@ -91,51 +92,75 @@ def _f64(a):
 
 
 # ---------------------------------------------------------------- lattice ---
-def lattice(D: int):
+# Lattice codes: 1, 2, 3 for the tensor-product lattices D1Q3, D2Q9, D3Q27;
+# 19 for D3Q19.
+D3Q19 = 19
+
+
+def lattice_Q(lat: int) -> int:
+    return 19 if lat == D3Q19 else 3 ** lat
+
+
+def lattice_D(lat: int) -> int:
+    return 3 if lat == D3Q19 else lat
+
+
+def lattice(lat: int):
     """(c[Q,3] int, W[Q] float64) in the library's direction order."""
-    Q = 3 ** D
+    Q = lattice_Q(lat)
     c = np.zeros((Q, 3), np.int32)
     W = np.zeros(Q, np.float64)
     q = C.c_int32()
-    rc = lib().orc_lattice(D, C.byref(q), c.ctypes.data_as(C.POINTER(C.c_int32)),
+    rc = lib().orc_lattice(lat, C.byref(q), c.ctypes.data_as(C.POINTER(C.c_int32)),
                            _dp(W))
     if rc:
-        raise ValueError(f"bad lattice dimension {D}")
+        raise ValueError(f"bad lattice code {lat}")
     return c, W
 
 
-def equilibrium(D, rho, u, poly=False):
+def equilibrium(lat, rho, u, poly=False):
     u3 = _f64(list(u) + [0.0] * (3 - len(u)))
-    out = np.zeros(3 ** D)
+    out = np.zeros(lattice_Q(lat))
     fn = lib().orc_equilibrium_poly if poly else lib().orc_equilibrium
-    if fn(D, float(rho), _dp(u3), _dp(out)):
-        raise ValueError("equilibrium undefined (rho <= 0 or |u_a| >= 1)")
+    if fn(lat, float(rho), _dp(u3), _dp(out)):
+        raise ValueError("equilibrium undefined (rho <= 0 or u outside the velocities' hull)")
     return out
 
 
-def moments_site(D, f):
+def equilibrium_minimiser(lat, rho, u):
+    """f^eq by Newton's method on the Lagrange multipliers (any lattice);
+    returns (feq, Newton iterations)."""
+    u3 = _f64(list(u) + [0.0] * (3 - len(u)))
+    out = np.zeros(lattice_Q(lat))
+    it = C.c_int32()
+    if lib().orc_equilibrium_minimiser(lat, float(rho), _dp(u3), _dp(out), C.byref(it)):
+        raise ValueError("no minimiser (rho <= 0, u outside the hull, or no convergence)")
+    return out, it.value
+
+
+def moments_site(lat, f):
     f = _f64(f)
     r = C.c_double()
     u = np.zeros(3)
-    lib().orc_moments_site(D, _dp(f), C.byref(r), _dp(u))
-    return r.value, u[:D]
+    lib().orc_moments_site(lat, _dp(f), C.byref(r), _dp(u))
+    return r.value, u[:lattice_D(lat)]
 
 
-def entropy(D, f):
-    return lib().orc_entropy(D, _dp(_f64(f)))
+def entropy(lat, f):
+    return lib().orc_entropy(lat, _dp(_f64(f)))
 
 
-def entropy_rel(D, g, feq):
-    return lib().orc_entropy_rel(D, _dp(_f64(g)), _dp(_f64(feq)))
+def entropy_rel(lat, g, feq):
+    return lib().orc_entropy_rel(lat, _dp(_f64(g)), _dp(_f64(feq)))
 
 
-def alpha_max(D, f, feq):
-    return lib().orc_alpha_max(D, _dp(_f64(f)), _dp(_f64(feq)))
+def alpha_max(lat, f, feq):
+    return lib().orc_alpha_max(lat, _dp(_f64(f)), _dp(_f64(feq)))
 
 
-def G(D, f, alpha):
+def G(lat, f, alpha):
     """H(f*(alpha)) - H(f) with f^eq computed from f's moments."""
-    return lib().orc_G(D, _dp(_f64(f)), float(alpha))
+    return lib().orc_G(lat, _dp(_f64(f)), float(alpha))
 
 
 # ------------------------------------------------------------ parameters ---
@@ -151,9 +176,16 @@ class Config:
     root_tol: float = 1e-13
     root_max_iter: int = 200
     nthreads: int = 1
+    q: int = 0            # 0: the tensor-product lattice 3^D; 19: D3Q19 (D = 3)
+
+    @property
+    def lattice(self) -> int:
+        if self.q not in (0, 19) or (self.q == 19 and self.D != 3):
+            raise ValueError(f"no lattice D{self.D}Q{self.q}")
+        return D3Q19 if self.q == 19 else self.D
 
     def params(self) -> Params:
-        return Params(self.D, self.nx, self.ny, self.nz, self.beta,
+        return Params(self.lattice, self.nx, self.ny, self.nz, self.beta,
                       MODES[self.mode], self.secant_iters, self.root_tol,
                       self.root_max_iter, self.nthreads)
 
@@ -163,7 +195,7 @@ class Config:
 
     @property
     def Q(self) -> int:
-        return 3 ** self.D
+        return lattice_Q(self.lattice)
 
 
 def _info_dict(si: SiteInfo) -> dict:

@@ -12,7 +12,16 @@ import numpy as np
 _DIGIT = {0: 0, 1: 1, 2: -1}
 
 
+def dim(lat: int) -> int:
+    """Dimension of a lattice code: 1, 2, 3 (D1Q3, D2Q9, D3Q27) or 19 (D3Q19)."""
+    return 3 if lat == 19 else lat
+
+
 def abi_velocities(D: int) -> np.ndarray:
+    if D == 19:
+        # D3Q19: the D3Q27 directions without the 8 corners, in D3Q27 order
+        c27 = abi_velocities(3)
+        return c27[np.count_nonzero(c27, axis=1) <= 2]
     Q = 3 ** D
     c = np.zeros((Q, 3), dtype=np.int64)
     for i in range(Q):
@@ -28,7 +37,8 @@ def abi_velocities(D: int) -> np.ndarray:
 # of non-zero velocity components.
 TEXTBOOK_W = {1: {0: (2, 3), 1: (1, 6)},
               2: {0: (4, 9), 1: (1, 9), 2: (1, 36)},
-              3: {0: (8, 27), 1: (2, 27), 2: (1, 54), 3: (1, 216)}}
+              3: {0: (8, 27), 1: (2, 27), 2: (1, 54), 3: (1, 216)},
+              19: {0: (1, 3), 1: (1, 18), 2: (1, 36)}}  # D3Q19 rest, face, edge
 
 
 def textbook_weights(D: int) -> np.ndarray:
@@ -39,9 +49,11 @@ def textbook_weights(D: int) -> np.ndarray:
 
 def lagrange_equilibrium(D: int, rho: float, u, iters: int = 60) -> np.ndarray:
     """Minimise H(g) = sum g ln(g/W) subject to sum g = rho, sum c g = rho u by
-    Newton's method on the Lagrange multipliers: g_i = W_i exp(l0 + l.c_i)."""
-    c = abi_velocities(D)[:, :D].astype(np.float64)
-    W = textbook_weights(D)
+    Newton's method on the Lagrange multipliers: g_i = W_i exp(l0 + l.c_i).
+    D is a lattice code (19: D3Q19)."""
+    lat, D = D, dim(D)
+    c = abi_velocities(lat)[:, :D].astype(np.float64)
+    W = textbook_weights(lat)
     A = np.hstack([np.ones((c.shape[0], 1)), c])  # [Q, D+1]
     target = np.concatenate([[rho], rho * np.asarray(u[:D], dtype=np.float64)])
     lam = np.zeros(D + 1)
@@ -59,9 +71,10 @@ def lagrange_equilibrium(D: int, rho: float, u, iters: int = 60) -> np.ndarray:
 
 def mp_lagrange_equilibrium(D: int, rho, u, dps: int = 50):
     """Same minimisation in mpmath arithmetic (returns a list of mpf)."""
+    lat, D = D, dim(D)
     with mp.workdps(dps):
-        c = abi_velocities(D)[:, :D]
-        W = mp_weights(D)
+        c = abi_velocities(lat)[:, :D]
+        W = mp_weights(lat)
         rho = mp.mpf(rho)
         uu = [mp.mpf(x) for x in u[:D]]
         lam = [mp.log(rho)] + [mp.mpf(0)] * D
@@ -112,7 +125,7 @@ def mp_G(D: int, f, alpha, dps: int = 50) -> mp.mpf:
         fm = [mp.mpf(float(v)) for v in f]
         rho = sum(fm)
         c = abi_velocities(D)
-        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(D)]
+        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(dim(D))]
         feq = mp_lagrange_equilibrium(D, rho, u, dps)
         W = mp_weights(D)
         a = mp.mpf(float(alpha))
@@ -130,7 +143,7 @@ def mp_root(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
         fm = [mp.mpf(float(v)) for v in f]
         rho = sum(fm)
         c = abi_velocities(D)
-        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(D)]
+        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(dim(D))]
         feq = mp_lagrange_equilibrium(D, rho, u, dps)
         W = mp_weights(D)
         H0 = mp_H(fm, W)
@@ -153,7 +166,7 @@ def mp_root(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
 def near_equilibrium_state(D: int, rho: float, u, eps: float, rng, feq_fn) -> np.ndarray:
     """f = f^eq (1 + eps xi) with xi projected so that f keeps the moments of
     f^eq (feq_fn supplies the equilibrium; the projection uses only 1 and c)."""
-    c = abi_velocities(D)[:, :D].astype(np.float64)
+    c = abi_velocities(D)[:, :dim(D)].astype(np.float64)
     feq = feq_fn(D, rho, u)
     A = np.hstack([np.ones((c.shape[0], 1)), c])
     xi = rng.standard_normal(c.shape[0])
