@@ -27,6 +27,13 @@
  *   - Directions: c_i in {-1,0,1}^D with i = d(c_x) + 3 d(c_y) + 9 d(c_z),
  *     d(0) = 0, d(+1) = 1, d(-1) = 2.  Weights W_i = prod_a w(c_ia),
  *     w(0) = 2/3, w(+-1) = 1/6 (D2Q9: 4/9, 1/9, 1/36).
+ *   - D3Q19 (ELBM_D3Q19) keeps the D3Q27 directions with at most two
+ *     nonzero components (no corners), in the order of their D3Q27 index,
+ *     with W = 1/3 (rest), 1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2).  Its weights
+ *     do not factorise, so f^eq (the minimiser of Eq. (3) under the mass and
+ *     momentum constraints) has no closed form: the step finds its Lagrange
+ *     multipliers per site by Newton's method.  Its domain is the interior
+ *     of the velocities' hull: |u_a| < 1 and |u_x| + |u_y| + |u_z| < 2.
  *   - Every array argument is a DEVICE pointer (hipMalloc'd or a torch
  *     tensor's data pointer) unless its comment says "host".  Population
  *     arrays are SoA float64: f[i*N + s]; velocity arrays are SoA u[a*N + s].
@@ -74,7 +81,9 @@ typedef enum {
   ELBM_EUNSUPPORTED = -5 /* combination not built into this library      */
 } elbm_status;
 
-enum { ELBM_D1Q3 = 1, ELBM_D2Q9 = 2, ELBM_D3Q27 = 3 };
+/* Lattice codes: D1Q3, D2Q9 and D3Q27 carry their dimension, D3Q19 its
+ * direction count. */
+enum { ELBM_D1Q3 = 1, ELBM_D2Q9 = 2, ELBM_D3Q27 = 3, ELBM_D3Q19 = 19 };
 
 enum {
   ELBM_ALPHA_CLOSED = 0, /* Eq. (8), acceptance test, Eq. (9)            */
@@ -104,7 +113,7 @@ enum {
 };
 
 typedef struct {
-  int32_t lattice;       /* ELBM_D1Q3 / ELBM_D2Q9 / ELBM_D3Q27            */
+  int32_t lattice;       /* ELBM_D1Q3 / ELBM_D2Q9 / ELBM_D3Q27 / ELBM_D3Q19 */
   int32_t nx, ny, nz;    /* box, each >= 1                                */
   double beta;           /* Eq. (2), 0 < beta < 1                         */
   int32_t alpha_mode;    /* ELBM_ALPHA_*                                  */
@@ -151,8 +160,9 @@ size_t elbm_state_bytes(const elbm_config *cfg);
 
 /* Create a simulation in the caller's device buffer dev_state (>= bytes of
  * elbm_state_bytes, 256-byte aligned) and set f(x,0) = f^eq(rho0(x), u0(x))
- * with rho0[N] > 0 and u0[D*N], |u0| < 1 per component (the domain of the
- * entropic equilibrium).  hip_stream is a hipStream_t (NULL = the null
+ * with rho0[N] > 0 and u0[D*N], |u0| < 1 per component and on D3Q19 also
+ * |u0_x| + |u0_y| + |u0_z| < 2 (the domain of the entropic equilibrium; D = 3
+ * and Q = 19 for D3Q19).  hip_stream is a hipStream_t (NULL = the null
  * stream).  Synchronises the stream once to validate rho0 and u0; returns
  * ELBM_EINVAL if any value is out of range.  *out receives the handle. */
 elbm_status elbm_init(const elbm_config *cfg, const double *rho0,

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libelbm.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
-SOURCES = ["elbm_step_d1.hip", "elbm_step_d2.hip", "elbm_step_d3.hip",
+SOURCES = ["elbm_step_d1.hip", "elbm_step_d2.hip", "elbm_step_d3.hip", "elbm_step_q19.hip",
            "elbm_aux.hip", "elbm_api.cpp", "elbm_serve.cpp"]
 HEADERS = ["elbm_site.hpp", "elbm_internal.hpp", "elbm_step_impl.hpp"]
 

@@ -52,7 +52,7 @@ int elem_size(int storage) {
 }
 
 struct Layout {
-  int D, Q, esize;
+  int lattice, D, Q, esize;
   int64_t N, padded;
   int nblocks;
   size_t off_buf[2], off_alpha, off_counts, off_sums, off_misc, total;
@@ -60,9 +60,9 @@ struct Layout {
 
 elbm_status check_config(const elbm_config* c, Layout* L) {
   if (!c) return fail(ELBM_EINVAL, "config is NULL");
-  if (c->lattice < ELBM_D1Q3 || c->lattice > ELBM_D3Q27)
+  if ((c->lattice < ELBM_D1Q3 || c->lattice > ELBM_D3Q27) && c->lattice != ELBM_D3Q19)
     return fail(ELBM_EINVAL, "unknown lattice %d", c->lattice);
-  const int D = c->lattice;
+  const int D = c->lattice == ELBM_D3Q19 ? 3 : c->lattice;
   if (c->nx < 1 || c->ny < 1 || c->nz < 1)
     return fail(ELBM_EINVAL, "box %d x %d x %d: every extent must be >= 1", c->nx, c->ny, c->nz);
   if (c->nx > kMaxDim || c->ny > kMaxDim || c->nz > kMaxDim)
@@ -96,11 +96,12 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   if ((c->diag & ELBM_DIAG_SUMS) && !(c->diag & ELBM_DIAG_COUNTS))
     return fail(ELBM_EINVAL, "ELBM_DIAG_SUMS needs ELBM_DIAG_COUNTS");
   if (c->reserved[0] != 0 || c->reserved[1] != 0) return fail(ELBM_EINVAL, "reserved must be 0");
-  if (!step_launcher(D, c->storage, c->alpha_mode, c->alpha_fp64))
+  if (!step_launcher(c->lattice, c->storage, c->alpha_mode, c->alpha_fp64))
     return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
 
+  L->lattice = c->lattice;
   L->D = D;
-  L->Q = D == 1 ? 3 : D == 2 ? 9 : 27;
+  L->Q = c->lattice == ELBM_D3Q19 ? 19 : D == 1 ? 3 : D == 2 ? 9 : 27;
   L->esize = es;
   L->N = N;
   // One workgroup per tiles_per_block() tiles of kBlock sites, rounded up to a
@@ -176,6 +177,7 @@ namespace {
 
 BoxDesc box_of(const elbm_sim* s) {
   BoxDesc b;
+  b.lattice = s->L.lattice;
   b.D = s->L.D;
   b.storage = s->cfg.storage;
   b.nx = s->cfg.nx;
@@ -314,7 +316,7 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
   s->device = dev;
   s->t = 0;
   s->have_alpha = s->have_stats = false;
-  s->launch = step_launcher(L.D, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64);
+  s->launch = step_launcher(cfg->lattice, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64);
 
   const BoxDesc b = box_of(s);
   unsigned long long nbad = 0;
@@ -330,7 +332,9 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
   if (nbad) {
     delete s;
     return fail(ELBM_EINVAL,
-                "%llu sites with rho0 <= 0 or |u0| >= 1 (outside the entropic equilibrium's domain)",
+                "%llu sites with rho0 <= 0 or u0 outside the hull of the velocities "
+                "(|u0_a| >= 1, or on D3Q19 |u0_x| + |u0_y| + |u0_z| >= 2): outside the "
+                "entropic equilibrium's domain",
                 nbad);
   }
   // Zero both buffers' padding once so that every byte of the state is
@@ -384,7 +388,7 @@ elbm_status elbm_step_batch(elbm_sim* const* sims, const int64_t* nsteps, int32_
     const elbm_sim* s = sims[k];
     if (!s) return fail(ELBM_EINVAL, "batch entry %d is NULL", k);
     if (nsteps[k] < 0) return fail(ELBM_EINVAL, "batch entry %d: nsteps < 0", k);
-    if (s->L.D != s0->L.D || s->cfg.storage != s0->cfg.storage ||
+    if (s->L.lattice != s0->L.lattice || s->cfg.storage != s0->cfg.storage ||
         s->cfg.alpha_mode != s0->cfg.alpha_mode || s->cfg.alpha_fp64 != s0->cfg.alpha_fp64)
       return fail(ELBM_EINVAL, "batch entry %d: lattice/storage/mode/precision differ", k);
     if (s->stream != s0->stream || s->device != s0->device)

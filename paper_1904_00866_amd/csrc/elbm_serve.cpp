@@ -52,6 +52,10 @@ constexpr size_t kPinnedCacheBytes = size_t(1) << 30;  // pinned copies kept for
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Dimension of a lattice code (ELBM_D1Q3 = 1, ELBM_D2Q9 = 2, ELBM_D3Q27 = 3,
+// ELBM_D3Q19 = 19); the config check rejects other codes.
+int lattice_dim(int32_t lattice) { return lattice == ELBM_D3Q19 ? 3 : lattice; }
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -239,7 +243,7 @@ void admit(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   for (size_t k = 0; k < take.size(); ++k) {
     Req* r = take[k].r;
     double* stage = reinterpret_cast<double*>(s->base + take[k].soff);
-    const size_t nbytes = size_t(r->N) * (1 + r->cfg.lattice) * sizeof(double);
+    const size_t nbytes = size_t(r->N) * (1 + lattice_dim(r->cfg.lattice)) * sizeof(double);
     if (hipMemcpyAsync(stage, r->host.p, nbytes, hipMemcpyHostToDevice, s->stream) == hipSuccess)
       st[k] = elbm::init_sim(&r->cfg, stage, stage + r->N, s->base + r->off, r->state_bytes,
                              s->stream, &r->sim, false);
@@ -494,13 +498,17 @@ elbm_status elbm_server_submit(elbm_server* s, const elbm_request* q, int64_t* i
     return set_error(ELBM_EINVAL, "out_rho and out_u must both be given or both be NULL");
   const size_t sb = elbm_state_bytes(&q->cfg);
   if (!sb) return ELBM_EINVAL;  // elbm_state_bytes has set the message
-  const int D = q->cfg.lattice;
+  const int D = lattice_dim(q->cfg.lattice);
   const int64_t N = int64_t(q->cfg.nx) * q->cfg.ny * q->cfg.nz;
   for (int64_t k = 0; k < N; ++k)
     if (!(q->rho0[k] > 0.0) || !std::isfinite(q->rho0[k]))
       return set_error(ELBM_EINVAL, "rho0 <= 0 or not finite");
   for (int64_t k = 0; k < int64_t(D) * N; ++k)
     if (!(std::fabs(q->u0[k]) < 1.0)) return set_error(ELBM_EINVAL, "|u0| >= 1 or not finite");
+  if (q->cfg.lattice == ELBM_D3Q19)
+    for (int64_t k = 0; k < N; ++k)
+      if (!(std::fabs(q->u0[k]) + std::fabs(q->u0[N + k]) + std::fabs(q->u0[2 * N + k]) < 2.0))
+        return set_error(ELBM_EINVAL, "|u0_x| + |u0_y| + |u0_z| >= 2 on D3Q19");
   auto r = std::make_unique<Req>();
   r->cfg = q->cfg;
   r->N = N;

@@ -228,7 +228,11 @@ template <int D, class S, class R>
 struct Site {
   using L = Lattice<D>;
   using T = typename S::T;
+  using Real = R;
   static constexpr int Q = L::Q;
+  static constexpr int kDim = D;
+  // f^eq_i = f01[dx][dy] e2[dz]: the common tier sums over c_z per (c_x, c_y)
+  static constexpr bool kZFactor = (D == 3);
   T raw[Q];
   R rho, irho, rho_ref;
   R u[3];
@@ -316,6 +320,18 @@ struct Site {
     }
   }
 
+  // H(f^eq) / rho = ln rho + sum_a (ln A_a + u_a ln z_a)
+  __device__ __forceinline__ double heq_per_rho() const {
+    double h = log((double)rho);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double ua = (double)u[a];
+      const double sa = sqrt(1.0 + 3.0 * ua * ua);
+      h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
+    }
+    return h;
+  }
+
   // -- loop accessors (run-time, wavefront-uniform i) -----------------------
   // Register arrays are never indexed at run time (that would move them to
   // scratch memory); the population is re-read from the source buffer,
@@ -335,11 +351,11 @@ struct Site {
 };
 
 // S(a) = sum_i f^eq_i phi((1 - a) x_i); G(a) = H(f*(a)) - H(f) = S(a) - D.
-template <int D, class S, class R>
-__device__ __forceinline__ R S_log(const Site<D, S, R>& v, R a) {
+template <class V, class R>
+__device__ __forceinline__ R S_log(const V& v, R a) {
   R s = R(0);
 #pragma unroll 1
-  for (int i = 0; i < Site<D, S, R>::Q; ++i) {
+  for (int i = 0; i < V::Q; ++i) {
     R xi, fi;
     v.xfe(i, xi, fi);
     s += fi * phi_log<R>((R(1) - a) * xi);
@@ -348,12 +364,12 @@ __device__ __forceinline__ R S_log(const Site<D, S, R>& v, R a) {
 }
 
 // S(a) and S'(a) = G'(a) = -sum_i f^eq_i x_i ln(1 + (1 - a) x_i).
-template <int D, class S, class R>
-__device__ __forceinline__ void S_dS_log(const Site<D, S, R>& v, R a, R& Sv, R& dS) {
+template <class V, class R>
+__device__ __forceinline__ void S_dS_log(const V& v, R a, R& Sv, R& dS) {
   Sv = R(0);
   dS = R(0);
 #pragma unroll 1
-  for (int i = 0; i < Site<D, S, R>::Q; ++i) {
+  for (int i = 0; i < V::Q; ++i) {
     R xi, fi;
     v.xfe(i, xi, fi);
     const R y = (R(1) - a) * xi;
@@ -365,10 +381,10 @@ __device__ __forceinline__ void S_dS_log(const Site<D, S, R>& v, R a, R& Sv, R& 
 
 // The rare path of one lane: the long series when alpha_* = 2 and
 // max|x| <= thrL, else the log1p forms.
-template <int D, class S, class R>
-__device__ __forceinline__ void rare_sums(const Site<D, S, R>& v, R astar, bool star2, R xabs, R& Dv, R& Ds,
+template <class V, class R>
+__device__ __forceinline__ void rare_sums(const V& v, R astar, bool star2, R xabs, R& Dv, R& Ds,
                           R& Gs) {
-  constexpr int Q = Site<D, S, R>::Q;
+  constexpr int Q = V::Q;
   if (star2 && xabs <= Base<R>::thrL) {
     R sE = R(0), sO = R(0);
     const SeriesK<R, Base<R>::KL> ser;
@@ -419,9 +435,12 @@ struct AlphaOut {
 enum { kPhaseAll = 0, kPhaseCommon = 1, kPhaseRare = 2 };
 
 // The choice of alpha at one site (all lanes of the wavefront call it).
-template <int MODE, int PHASE, int D, class S, class R>
-__device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimDesc& d) {
-  constexpr int Q = Site<D, S, R>::Q;
+// V: the site type (lattice, storage, arithmetic).
+template <int MODE, int PHASE, class V>
+__device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const SimDesc& d) {
+  using R = typename V::Real;
+  constexpr int D = V::kDim;
+  constexpr int Q = V::Q;
   AlphaOut<R> o;
   o.deferred = false;
   // The root solvers need alpha_max on every lane; the closed form and the
@@ -433,7 +452,7 @@ __device__ __forceinline__ AlphaOut<R> choose_alpha(Site<D, S, R>& v, const SimD
   if constexpr (PHASE != kPhaseRare) {
   const SeriesK<R, Base<R>::K> ser;
   const auto P = v.pass();
-  if constexpr (D == 3) {
+  if constexpr (V::kZFactor) {
     // f^eq_i = f01[dx][dy] e2[dz]: the sums over dz are formed with e2
     // alone and multiplied by f01 once per (dx, dy)
 #pragma unroll
@@ -875,10 +894,11 @@ struct SiteOut {
 
 // Diagnostics of one updated site of an entropic mode: per-lane values
 // here, count predicates returned.
-template <int D, class S, class R, bool SUMS>
+template <bool SUMS, class V, class R>
 __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bool live,
-                                            const Site<D, S, R>& v, const AlphaOut<R>& ao,
+                                            const V& v, const AlphaOut<R>& ao,
                                             R ftmin, const R (&j)[3], Acc& acc, int diag) {
+  constexpr int D = V::kDim;
   const R alpha = ao.alpha, rho = v.rho;
   uint32_t flags = 0;
   if (diag & kDiagCounts) {
@@ -889,15 +909,8 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
               flag(kCntNonfinite, !isfinite(rho * alpha * v.u[0] * v.u[1] * v.u[2] + rho));
     if (live) acc.iters += ao.iters;
     if (SUMS && live && (diag & kDiagSums)) {
-      // H(f) = H(f^eq) + D, H(f^eq) = rho [ln rho + sum_a (ln A_a + u_a ln z_a)]
-      double h = log((double)rho);
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double ua = (double)v.u[a];
-        const double sa = sqrt(1.0 + 3.0 * ua * ua);
-        h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
-      }
-      acc.H += (double)rho * h + (double)ao.D;
+      // H(f) = H(f^eq) + D
+      acc.H += (double)rho * v.heq_per_rho() + (double)ao.D;
     }
   }
   if (diag & kDiagAlpha) d.alpha[s] = (double)alpha;
@@ -996,7 +1009,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
       st_nt<T>(blk + i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, R(L::invW(i)), v.rho_ref));
       sched_group(i);
     }
-    return SiteOut{false, record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
+    return SiteOut{false, record_site<SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
   }
 }
 
@@ -1034,7 +1047,7 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
     const R invW = R(L::den()) / R(nz0 == 0 ? 1.0 : nz0 == 1 ? 4.0 : nz0 == 2 ? 16.0 : 64.0);
     st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, invW, v.rho_ref));
   }
-  return record_site<D, S, R, SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
+  return record_site<SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
 }
 
 // One workgroup per ELBM_TILES tiles of kBlock consecutive sites; the loads

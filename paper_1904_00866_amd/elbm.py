@@ -17,8 +17,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libelbm.so")
 
-D1Q3, D2Q9, D3Q27 = 1, 2, 3
-LATTICES = {"d1q3": D1Q3, "d2q9": D2Q9, "d3q27": D3Q27}
+D1Q3, D2Q9, D3Q27, D3Q19 = 1, 2, 3, 19
+LATTICES = {"d1q3": D1Q3, "d2q9": D2Q9, "d3q27": D3Q27, "d3q19": D3Q19}
+
+
+def lattice_dq(code: int):
+    """(D, Q) of a lattice code."""
+    return (3, 19) if code == D3Q19 else (code, 3 ** code)
 MODES = {"closed": 0, "newton": 1, "bisect": 2, "bgk": 3, "secant": 4}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 DIAG_ALPHA, DIAG_COUNTS, DIAG_SUMS = 1, 2, 4
@@ -182,8 +187,7 @@ class Simulation:
     def __init__(self, lattice, nx, ny=1, nz=1, *, rho0, u0, device="cuda",
                  stream: Optional[torch.cuda.Stream] = None, **kw):
         self.cfg = make_config(lattice, nx, ny, nz, **kw)
-        self.D = self.cfg.lattice
-        self.Q = 3 ** self.D
+        self.D, self.Q = lattice_dq(self.cfg.lattice)
         self.N = nx * ny * nz
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
@@ -293,8 +297,7 @@ class KeptSimulation(Simulation):
 
     def __init__(self, server: "Server", rid: int, cfg: Config, handle):
         self.cfg = cfg
-        self.D = cfg.lattice
-        self.Q = 3 ** self.D
+        self.D, self.Q = lattice_dq(cfg.lattice)
         self.N = cfg.nx * cfg.ny * cfg.nz
         self.device = server.device
         self.stream = server.stream

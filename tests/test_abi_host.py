@@ -67,6 +67,26 @@ def test_default_config_and_state_bytes():
     assert elbm.state_bytes(cfgd) >= nb + 8 * 64 ** 3
 
 
+def test_d3q19_config_and_state_bytes():
+    """D3Q19 (lattice code 19) is a three-dimensional lattice of 19
+    directions: two buffers of 19 populations per (padded) site; the codes
+    4..18 are no lattice."""
+    cfg = elbm.make_config("d3q19", 64, 64, 64)
+    assert cfg.lattice == 19 and elbm.lattice_dq(19) == (3, 19)
+    nb = elbm.state_bytes(cfg)
+    assert 2 * 19 * 64 ** 3 * 4 <= nb < 2 * 19 * (64 ** 3 + 2048) * 4 + 65536
+    assert elbm.state_bytes(elbm.make_config("d3q19", 64, 64, 64, storage="f64")) > nb
+    for mode in ("closed", "newton", "bisect", "bgk", "secant"):
+        assert elbm.state_bytes(elbm.make_config("d3q19", 8, 8, 8, mode=mode)) > 0
+    assert elbm.state_bytes(elbm.make_config("d3q19", 8, 8, 8, fp64=False)) > 0
+    for bad in (4, 9, 18, 27):
+        c = elbm.make_config("d3q27", 8, 8, 8)
+        c.lattice = bad
+        assert elbm.lib().elbm_state_bytes(C.byref(c)) == 0
+        with pytest.raises(elbm.ElbmError, match="unknown lattice"):
+            elbm.state_bytes(c)
+
+
 def test_large_boxes_fit_the_layout():
     """A 1024^3 FP32 D3Q27 state (232 GB with both buffers) is a valid
     configuration: the blocked layout has no per-buffer size limit."""
