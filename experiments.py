@@ -14,6 +14,11 @@ is needed; its parity with the CPU oracle is established by the GPU tests).
                                  FP64 / FP32 / FP32-dev / FP16-dev under both
                                  precision policies: velocity and kinetic-energy
                                  error vs FP64, per-site H increases
+    python experiments.py f3     D3Q19 beside D3Q27: 512^3 FP32 step time and
+                                 HBM roofline fraction of the closed form, LBGK
+                                 and (256^3) Newton; 128^3 Re = 1600 Taylor-Green:
+                                 kinetic-energy decay and the share of sites
+                                 with alpha < 2 on both lattices
 Each prints one JSON object per experiment on stdout.
 """
 from __future__ import annotations
@@ -239,10 +244,91 @@ def w4(n=256, T=2000):
     return out
 
 
+# --------------------------------------------------------------------- F3 --
+HBM_PEAK_GBS = 8000.0
+
+
+def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
+       modes=("closed", "bgk", "newton"), lattices=("d3q19", "d3q27")):
+    out = {"experiment": "f3", "workload": f"3-D Taylor-Green (u0 = 0.05, Re = 1600), FP32 "
+           f"storage, FP64 site arithmetic: step timing at {n}^3 (Newton {newton_n}^3), "
+           f"{steps} timed steps after 3 warm-up; limiter statistics at {tgv_n}^3 over "
+           f"{tgv_steps} steps", "timing": {}, "tgv": {}}
+    if copy_mib:
+        # a plain copy of known size, for scaling the HBM counters of a
+        # profiler run of this command
+        a = torch.empty(copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    fields = {}
+    for lat in lattices:
+        Q = 19 if lat == "d3q19" else 27
+        for mode in modes:
+            m = newton_n if mode == "newton" else n
+            N = m ** 3
+            if m not in fields:
+                fields[m] = Wk.taylor_green_3d(m)
+            rho, u = fields[m]
+            with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage="f32", mode=mode,
+                                 beta=Wk.tgv3d_beta(m)) as sim:
+                sim.step(3)
+                k = steps if mode != "newton" else 3
+                ms = _timed_steps(sim, k)
+            gbs = 2.0 * Q * 4 * N / (ms * 1e-3) / 1e9
+            out["timing"][f"{lat}_{mode}"] = {
+                "n": m, "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+                "algorithmic_gb_per_step": round(2.0 * Q * 4 * N / 1e9, 4),
+                "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            log(f"f3 {lat} {mode} {m}^3: {out['timing'][f'{lat}_{mode}']}")
+            torch.cuda.empty_cache()
+    fields.clear()
+    for lat in lattices if tgv_steps > 0 else ():
+        m = tgv_n
+        rho, u = Wk.taylor_green_3d(m)
+        rec = []
+        with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage="f32",
+                             beta=Wk.tgv3d_beta(m), diag=elbm.DIAG_COUNTS) as sim:
+            r, v = sim.moments()
+            ke0 = _kinetic(r, v)
+            for t in range(250, tgv_steps + 1, 250):
+                sim.step(249)
+                sim.step(1)
+                st = sim.stats()
+                r, v = sim.moments()
+                torch.cuda.synchronize()
+                rec.append({"t": t, "ke_ratio": _kinetic(r, v) / ke0,
+                            "alpha_lt2_frac": st["n_alpha_lt2"] / st["n_sites"],
+                            "alpha_min": st["alpha_min"],
+                            "alphastar_lt2": st["n_alphastar_lt2"]})
+        out["tgv"][lat] = rec
+        log(f"f3 tgv {lat}: {rec[-1]}")
+    if len(out["tgv"]) == 2:
+        a19, a27 = out["tgv"]["d3q19"], out["tgv"]["d3q27"]
+        out["tgv_ke_ratio_diff_max"] = max(abs(x["ke_ratio"] - y["ke_ratio"])
+                                           for x, y in zip(a19, a27))
+    T = out["timing"]
+    if "d3q19_closed" in T and "d3q27_closed" in T:
+        out["q19_closed_over_q27_closed_mlups"] = round(
+            T["d3q19_closed"]["mlups"] / T["d3q27_closed"]["mlups"], 3)
+    if "d3q19_closed" in T and "d3q19_newton" in T:
+        out["q19_closed_over_newton"] = round(
+            T["d3q19_closed"]["mlups"] / T["d3q19_newton"]["mlups"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4"])
+    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "f3"])
     ap.add_argument("--w2-steps", type=int, default=20000)
+    ap.add_argument("--f3-n", type=int, default=512)
+    ap.add_argument("--f3-steps", type=int, default=20)
+    ap.add_argument("--f3-tgv-steps", type=int, default=2000)
+    ap.add_argument("--f3-modes", default="closed,bgk,newton")
+    ap.add_argument("--f3-lattices", default="d3q19,d3q27")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one torch copy of this many MiB first (HBM counter scale)")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         print("experiments.py needs a GPU", file=sys.stderr)
@@ -250,7 +336,12 @@ def main():
     elbm.lib()
     for w in args.which:
         t0 = time.time()
-        res = {"w1": w1, "e2": e2, "w4": w4}.get(w, lambda: w2(args.w2_steps))()
+        res = {"w1": w1, "e2": e2, "w4": w4,
+               "f3": lambda: f3(n=args.f3_n, steps=args.f3_steps,
+                                tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
+                                modes=tuple(args.f3_modes.split(",")),
+                                lattices=tuple(args.f3_lattices.split(",")))
+               }.get(w, lambda: w2(args.w2_steps))()
         res["wall_s"] = round(time.time() - t0, 1)
         print(json.dumps(res), flush=True)
     return 0

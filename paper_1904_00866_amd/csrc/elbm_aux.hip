@@ -6,6 +6,7 @@
 // P_i(x - c_i) = f_i(x, t), i.e. the post-collision values of the previous
 // step before streaming (Eq. (5b) is carried out by the reader).
 #include "elbm_internal.hpp"
+#include "elbm_q19.hpp"
 #include "elbm_site.hpp"
 
 namespace elbm {

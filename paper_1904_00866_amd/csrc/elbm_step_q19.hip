@@ -15,6 +15,7 @@
 //     opposite direction's f^eq.
 // The choice of alpha (tiers, modes, diagnostics) is the lattice-independent
 // code of the tensor-product kernel.
+#include "elbm_q19.hpp"
 #include "elbm_step_impl.hpp"
 
 namespace elbm {
