@@ -14,12 +14,16 @@ from paper_1904_00866_amd import workloads as Wk
 pytestmark = pytest.mark.gpu
 
 
+def _dim(D):
+    return 3 if D == 19 else D  # lattice code 19: D3Q19
+
+
 def _fields(D, shape, seed):
     N = int(np.prod(shape))
     if D == 2 and shape[0] == shape[1]:
         rho, u = Wk.shear_layer(shape[0])
         return rho.reshape(-1), u.reshape(2, -1)
-    rho, u = Wk.random_velocity_field(D, N, 0.05, seed=seed)
+    rho, u = Wk.random_velocity_field(_dim(D), N, 0.05, seed=seed)
     return rho, u
 
 
@@ -44,11 +48,13 @@ MIX = [  # (D, shape, steps, kwargs)
     (3, (20, 20, 20), 30, dict(storage="f16dev", beta=0.99)),
     (2, (64, 64, 1), 120, dict(storage="f32", beta=0.99)),
     (2, (50, 50, 1), 333, dict(storage="f32", beta=0.96, mode="secant")),
+    (19, (14, 10, 9), 50, dict(storage="f32", beta=0.98)),
+    (19, (16, 16, 16), 80, dict(storage="f16dev", beta=0.99)),
 ]
 
 
 def test_server_mix_equals_alone(gpu):
-    """Twelve requests of mixed lattices, sizes, storages, modes and step
+    """Fourteen requests of mixed lattices, sizes, storages, modes and step
     counts, arriving while earlier ones run (5 slots, 37-step rounds): the
     final rho, u of each equal those of the same simulation advanced alone."""
     dev = torch.device("cuda")
@@ -60,7 +66,7 @@ def test_server_mix_equals_alone(gpu):
             N = int(np.prod(shp))
             with torch.cuda.stream(stream):
                 o = (torch.empty(N, dtype=torch.float64, device=dev),
-                     torch.empty(D, N, dtype=torch.float64, device=dev))
+                     torch.empty(_dim(D), N, dtype=torch.float64, device=dev))
             outs.append(o)
             ids.append(srv.submit(D, *shp, rho0=rho, u0=u, nsteps=steps, out_rho=o[0],
                                   out_u=o[1], **kw))
