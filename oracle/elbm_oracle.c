@@ -17,6 +17,10 @@
  * the modified secant iteration of the closing remark.  LBGK (alpha = 2 with
  * the polynomial equilibrium) is the special case named after Eq. (4).
  *
+ * The paper states the scheme for the Boltzmann entropy of Eq. (3) and
+ * remarks that the formula holds for any convex entropy; the oracle also
+ * runs it with Burg's entropy H(f) = -sum_i W_i ln(f_i / W_i).
+ *
  * Readings of points the paper leaves open (each one is listed with its
  * reason in the design notes of the repository):
  *   - lattice units, c_s^2 = 1/3, tensor-product weights W = (2/3,1/6,1/6)^D;
@@ -29,7 +33,11 @@
  *   - 0 ln 0 = 0; alpha_max = +inf when no i has f_i^eq < f_i;
  *   - when f = f^eq to rounding (D(f) <= 1e-26 rho, or alpha_max = +inf),
  *     alpha := alpha_* (the paper: alpha is then arbitrary);
- *   - Eq. (9)'s result is clamped to [1, alpha_*], where it lies exactly.
+ *   - Eq. (9)'s result is clamped to [1, alpha_*], where it lies exactly;
+ *   - with Burg's entropy, which is infinite at a zero population, alpha_* =
+ *     alpha_max < 2 makes both entropy differences of Eq. (9) infinite: their
+ *     ratio is 1 in the limit, so Eq. (9) (and the modified secant) give
+ *     alpha = 1.
  */
 #include "elbm_oracle.h"
 
@@ -43,9 +51,12 @@
 #define QMAX 27
 #define GUARD_REL 1e-26
 
+enum { ENT_BOLTZMANN = 0, ENT_BURG = 1 };
+
 typedef struct {
   int D, Q;
   int product;          /* weights factorise per axis (D1Q3, D2Q9, D3Q27)  */
+  int ent;              /* ENT_BOLTZMANN (Eq. (3)) or ENT_BURG              */
   int c[QMAX][3];
   double W[QMAX];
 } lat_t;
@@ -60,6 +71,7 @@ typedef struct {
  * the order of their D3Q27 index, with the standard weights 1/3 (rest),
  * 1/18 (|c|^2 = 1) and 1/36 (|c|^2 = 2). */
 static int make_lattice(int code, lat_t *L) {
+  L->ent = ENT_BOLTZMANN;
   if (code == 19) {
     L->D = 3;
     L->Q = 0;
@@ -101,6 +113,15 @@ static int make_lattice(int code, lat_t *L) {
     for (int k = 0; k < nzero; ++k) num *= 4.0;
     L->W[i] = num / den;
   }
+  return 0;
+}
+
+/* Model code of the single-state functions: lattice code + 256 x entropy
+ * (0: the Boltzmann entropy of Eq. (3), 1: Burg's entropy). */
+static int make_model(int code, lat_t *L) {
+  const int ent = code >> 8;
+  if (code < 0 || ent > ENT_BURG || make_lattice(code & 255, L)) return -1;
+  L->ent = ent;
   return 0;
 }
 
@@ -263,10 +284,116 @@ static int equilibrium_minimiser(const lat_t *L, double rho, const double *u,
   return iters;
 }
 
-/* f^eq by the closed product form where the weights factorise, else by the
+/* Burg's entropy H(f) = -sum_i W_i ln(f_i / W_i): stationarity of the
+ * Lagrangian gives W_i / f_i = m0 + m.c_i, i.e. f_i = W_i / (mu.a_i) with
+ * a_i = (1, c_i) and mu = (m0, m).  mu maximises the concave dual
+ *   g(mu) = sum_i W_i ln(mu.a_i) - mu.b,   b = (rho, rho u),
+ * whose gradient sum_i W_i a_i / (mu.a_i) - b is the constraint residual
+ * and whose Hessian is -sum_i W_i a_i a_i^T / (mu.a_i)^2.  Newton's method on
+ * g from the rest state mu = (1/rho, 0), halving a step while it would make
+ * some mu.a_i non-positive or fail to increase g (Armijo); it stops after a
+ * step below 1e-12 (m0 is of order 1/rho).  Returns the iteration count, or
+ * -1 (feq NaN) without convergence. */
+static int burg_dual(const lat_t *L, const double *mu, const double *b, double *g,
+                     double *grad, double H[4][4]) {
+  const int n = L->D + 1;
+  double v = 0.0, s[4] = {0.0, 0.0, 0.0, 0.0}, S[4][4] = {{0.0}};
+  for (int i = 0; i < L->Q; ++i) {
+    double a[4] = {1.0, L->c[i][0], L->c[i][1], L->c[i][2]};
+    double d = 0.0;
+    for (int k = 0; k < n; ++k) d += mu[k] * a[k];
+    if (!(d > 0.0)) return -1;
+    v += L->W[i] * log(d);
+    for (int k = 0; k < n; ++k) {
+      s[k] += L->W[i] * a[k] / d;
+      for (int m = 0; m < n; ++m) S[k][m] += L->W[i] * a[k] * a[m] / (d * d);
+    }
+  }
+  for (int k = 0; k < n; ++k) v -= mu[k] * b[k];
+  *g = v;
+  if (grad)
+    for (int k = 0; k < n; ++k) {
+      grad[k] = s[k] - b[k];
+      for (int m = 0; m < n; ++m) H[k][m] = S[k][m];  /* -Hessian, positive definite */
+    }
+  return 0;
+}
+
+static int solve4(int n, double A[4][4], const double *r, double *x) {
+  double M[4][5];
+  for (int a = 0; a < n; ++a) {
+    for (int b = 0; b < n; ++b) M[a][b] = A[a][b];
+    M[a][n] = r[a];
+  }
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int a = k + 1; a < n; ++a)
+      if (fabs(M[a][k]) > fabs(M[piv][k])) piv = a;
+    if (M[piv][k] == 0.0) return -1;
+    for (int b = 0; b <= n; ++b) {
+      double t = M[k][b];
+      M[k][b] = M[piv][b];
+      M[piv][b] = t;
+    }
+    for (int a = k + 1; a < n; ++a) {
+      double f = M[a][k] / M[k][k];
+      for (int b = k; b <= n; ++b) M[a][b] -= f * M[k][b];
+    }
+  }
+  for (int a = n - 1; a >= 0; --a) {
+    double v = M[a][n];
+    for (int b = a + 1; b < n; ++b) v -= M[a][b] * x[b];
+    x[a] = v / M[a][a];
+  }
+  return 0;
+}
+
+static int equilibrium_burg(const lat_t *L, double rho, const double *u, double *feq) {
+  const int n = L->D + 1;
+  double mu[4] = {1.0 / rho, 0.0, 0.0, 0.0}, b[4] = {rho, 0.0, 0.0, 0.0};
+  for (int a = 0; a < L->D; ++a) b[a + 1] = rho * u[a];
+  int iters = -1;
+  for (int it = 1; it <= 80; ++it) {
+    double g, grad[4], H[4][4], d[4];
+    if (burg_dual(L, mu, b, &g, grad, H) || solve4(n, H, grad, d)) break;
+    /* ascent direction d = (-Hessian)^-1 grad */
+    double dmax = 0.0, slope = 0.0;
+    for (int k = 0; k < n; ++k) {
+      if (fabs(d[k]) > dmax) dmax = fabs(d[k]);
+      slope += grad[k] * d[k];
+    }
+    double t = 1.0;
+    for (int k = 0; k < 60; ++k) {
+      double mt[4], gt;
+      for (int m = 0; m < n; ++m) mt[m] = mu[m] + t * d[m];
+      if (!burg_dual(L, mt, b, &gt, NULL, NULL) && (dmax <= 1e-6 || gt >= g + 1e-4 * t * slope))
+        break;
+      t *= 0.5;
+    }
+    for (int k = 0; k < n; ++k) mu[k] += t * d[k];
+    if (t * dmax <= 1e-12) {
+      iters = it;
+      break;
+    }
+  }
+  if (iters < 0) {
+    for (int i = 0; i < L->Q; ++i) feq[i] = NAN;
+    return -1;
+  }
+  for (int i = 0; i < L->Q; ++i) {
+    double d = mu[0];
+    for (int a = 0; a < L->D; ++a) d += mu[a + 1] * L->c[i][a];
+    feq[i] = L->W[i] / d;
+  }
+  return iters;
+}
+
+/* f^eq: for the Boltzmann entropy by the closed product form where the
+ * weights factorise, else by the minimiser; for Burg's entropy by its own
  * minimiser. */
 static void equilibrium(const lat_t *L, double rho, const double *u, double *feq) {
-  if (L->product) equilibrium_product(L, rho, u, feq);
+  if (L->ent == ENT_BURG) (void)equilibrium_burg(L, rho, u, feq);
+  else if (L->product) equilibrium_product(L, rho, u, feq);
   else (void)equilibrium_minimiser(L, rho, u, feq);
 }
 
@@ -284,29 +411,56 @@ static void equilibrium_poly(const lat_t *L, double rho, const double *u,
 }
 
 /* ---- entropy --------------------------------------------------------------
- * Eq. (3) literally, with 0 ln 0 = 0; NaN for a negative population. */
+ * Eq. (3) literally, with 0 ln 0 = 0; NaN for a negative population.  Burg:
+ * -sum_i W_i ln(f_i / W_i), +inf at a zero population. */
 static double entropy(const lat_t *L, const double *f) {
   double h = 0.0;
   for (int i = 0; i < L->Q; ++i) {
     if (f[i] < 0.0) return NAN;
-    if (f[i] > 0.0) h += f[i] * log(f[i] / L->W[i]);
+    if (L->ent == ENT_BURG) {
+      if (f[i] == 0.0) return INFINITY;
+      h -= L->W[i] * log(f[i] / L->W[i]);
+    } else if (f[i] > 0.0) {
+      h += f[i] * log(f[i] / L->W[i]);
+    }
   }
   return h;
 }
 
-/* phi(y) = (1+y) ln(1+y) - y >= 0, the relative-entropy density.
- * Because ln(f_i^eq/W_i) = l0 + l.c_i is affine in (1, c_i), every g with the
- * moments of f^eq satisfies sum_i g_i ln(f_i^eq/W_i) = H(f^eq), and therefore
- *   H(g) - H(f^eq) = sum_i f_i^eq phi(g_i/f_i^eq - 1).
- * This is an identity, not an approximation; it avoids subtracting two
- * O(rho) entropies to get an O(rho eps^3) difference.  phi(-1) = 1 is the
- * 0 ln 0 = 0 limit (a population that is exactly zero).  At alpha = alpha_max
- * the component that defines alpha_max has f*_k = 0 exactly, but the rounded
- * y_k = (1 - alpha_max) x_k can land an ulp below -1; every y <= -1 met here
- * is that rounding, so it is read as f*_k = 0. */
+/* Relative-entropy densities.  For an entropy H(f) = sum_i h_i(f_i) whose
+ * equilibrium makes h_i'(f_i^eq) affine in (1, c_i), every g with the
+ * moments of f^eq satisfies sum_i (g_i - f_i^eq) h_i'(f_i^eq) = 0, so
+ *   H(g) - H(f^eq) = sum_i w_i psi(g_i / f_i^eq - 1)
+ * exactly, without the cancellation of two O(rho) entropies:
+ *   Boltzmann (Eq. (3)): w_i = f_i^eq, psi = phi, phi(y) = (1+y) ln(1+y) - y;
+ *   Burg:                w_i = W_i,    psi = chi, chi(y) = y - ln(1+y).
+ * phi(-1) = 1 is the 0 ln 0 = 0 limit (a population that is exactly zero);
+ * chi(-1) = +inf.  At alpha = alpha_max the component that defines alpha_max
+ * has f*_k = 0 exactly, but the rounded y_k = (1 - alpha_max) x_k can land an
+ * ulp below -1; every y <= -1 met here is that rounding, so it is read as
+ * f*_k = 0. */
 static double phi(double y) {
   if (y <= -1.0) return 1.0;
   return (1.0 + y) * log1p(y) - y;
+}
+
+static double chi(double y) {
+  if (y <= -1.0) return INFINITY;
+  return y - log1p(y);
+}
+
+static double psi(const lat_t *L, double y) {
+  return L->ent == ENT_BURG ? chi(y) : phi(y);
+}
+
+/* psi'(y): ln(1 + y) (Boltzmann), y / (1 + y) (Burg). */
+static double dpsi(const lat_t *L, double y) {
+  if (L->ent == ENT_BURG) return y <= -1.0 ? -INFINITY : y / (1.0 + y);
+  return log1p(y < -1.0 ? -1.0 : y);
+}
+
+static double weight_of(const lat_t *L, const double *feq, int i) {
+  return L->ent == ENT_BURG ? L->W[i] : feq[i];
 }
 
 /* x_i = f_i / f_i^eq - 1, formed as (f_i - f_i^eq) / f_i^eq. */
@@ -317,31 +471,29 @@ static void deviations(const lat_t *L, const double *f, const double *feq,
 
 /* f*(alpha) = f + alpha (f^eq - f) = f^eq (1 + (1 - alpha) x), so
  *   G(alpha) := H(f*(alpha)) - H(f)
- *             = sum_i f_i^eq [phi((1 - alpha) x_i) - phi(x_i)].          */
+ *             = sum_i w_i [psi((1 - alpha) x_i) - psi(x_i)].            */
 static double G_of(const lat_t *L, const double *feq, const double *x,
                    double alpha) {
   double g = 0.0;
   for (int i = 0; i < L->Q; ++i)
-    g += feq[i] * (phi((1.0 - alpha) * x[i]) - phi(x[i]));
+    g += weight_of(L, feq, i) * (psi(L, (1.0 - alpha) * x[i]) - psi(L, x[i]));
   return g;
 }
 
-/* G'(alpha) = -sum_i f_i^eq x_i ln(1 + (1 - alpha) x_i). */
+/* G'(alpha) = -sum_i w_i x_i psi'((1 - alpha) x_i). */
 static double dG_of(const lat_t *L, const double *feq, const double *x,
                     double alpha) {
   double g = 0.0;
-  for (int i = 0; i < L->Q; ++i) {
-    double y = (1.0 - alpha) * x[i];
-    g -= feq[i] * x[i] * log1p(y < -1.0 ? -1.0 : y);
-  }
+  for (int i = 0; i < L->Q; ++i)
+    g -= weight_of(L, feq, i) * x[i] * dpsi(L, (1.0 - alpha) * x[i]);
   return g;
 }
 
-/* H(f*(alpha)) - H(f^eq) = sum_i f_i^eq phi((1 - alpha) x_i)  (Eq. (9) denominator) */
+/* H(f*(alpha)) - H(f^eq) = sum_i w_i psi((1 - alpha) x_i)  (Eq. (9) denominator) */
 static double Hrel_of(const lat_t *L, const double *feq, const double *x,
                       double alpha) {
   double h = 0.0;
-  for (int i = 0; i < L->Q; ++i) h += feq[i] * phi((1.0 - alpha) * x[i]);
+  for (int i = 0; i < L->Q; ++i) h += weight_of(L, feq, i) * psi(L, (1.0 - alpha) * x[i]);
   return h;
 }
 
@@ -413,16 +565,18 @@ static double choose_alpha(const lat_t *L, const orc_params *p, const double *f,
   double astar = (amax < 2.0) ? amax : 2.0;        /* Eq. (8) */
   double Dv = Hrel_of(L, feq, x, 0.0);              /* H(f) - H(f^eq) */
   int guard = (Dv <= GUARD_REL * rho) || isinf(amax);
-  double Gs = guard ? 0.0 : G_of(L, feq, x, astar); /* H(f*(a_*)) - H(f) */
+  /* Burg's entropy is infinite at the zero population of f*(alpha_max) */
+  const int inf_star = (L->ent == ENT_BURG) && astar == amax;
+  double Gs = guard ? 0.0 : inf_star ? INFINITY : G_of(L, feq, x, astar); /* H(f*(a_*)) - H(f) */
   double alpha = astar;
   int iters = 0;
 
   if (!guard) {
     if (p->mode == ORC_ALPHA_CLOSED) {
       if (Gs > 0.0) {
-        /* Eq. (9) */
-        double den = Hrel_of(L, feq, x, astar);     /* H(f*(a_*)) - H(f^eq) */
-        alpha = astar + Gs / den * (1.0 - astar);
+        /* Eq. (9); both differences infinite: their ratio's limit is 1 */
+        double ratio = inf_star ? 1.0 : Gs / Hrel_of(L, feq, x, astar); /* den: H(f*(a_*)) - H(f^eq) */
+        alpha = astar + ratio * (1.0 - astar);
         if (alpha < 1.0) alpha = 1.0;
         if (alpha > astar) alpha = astar;
         iters = 1;
@@ -433,13 +587,15 @@ static double choose_alpha(const lat_t *L, const orc_params *p, const double *f,
          * alpha^(0) = 1 (G(1) = H(f^eq) - H(f)) so that the first iterate
          * is Eq. (9). */
         double a = 1.0;
-        for (int k = 0; k < p->secant_iters; ++k) {
+        /* G(a_*) infinite: every iterate stays at alpha^(0) = 1 */
+        for (int k = 0; k < (inf_star ? 0 : p->secant_iters); ++k) {
           double Ga = G_of(L, feq, x, a);
           double an = astar + Gs / (Gs - Ga) * (a - astar);
           iters = k + 1;
           if (an == a) break;
           a = an;
         }
+        if (inf_star) iters = 1;
         if (a < 1.0) a = 1.0;
         if (a > astar) a = astar;
         alpha = a;
@@ -466,6 +622,8 @@ static double choose_alpha(const lat_t *L, const orc_params *p, const double *f,
 static int check_params(const orc_params *p, lat_t *L) {
   if (!p) return -1;
   if (make_lattice(p->lattice, L)) return -1;
+  if (p->entropy != ENT_BOLTZMANN && p->entropy != ENT_BURG) return -1;
+  L->ent = p->entropy;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
   if (L->D == 1 && (p->ny != 1 || p->nz != 1)) return -1;
   if (L->D == 2 && p->nz != 1) return -1;
@@ -508,7 +666,7 @@ static void collide(const lat_t *L, const orc_params *p, const double *f,
 /* ---- exported single-state functions ------------------------------------ */
 int orc_lattice(int32_t lattice, int32_t *Q, int32_t *c, double *W) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return -1;
+  if (make_model(lattice, &L)) return -1;
   if (Q) *Q = L.Q;
   for (int i = 0; i < L.Q; ++i) {
     if (c)
@@ -520,7 +678,7 @@ int orc_lattice(int32_t lattice, int32_t *Q, int32_t *c, double *W) {
 
 int orc_equilibrium(int32_t lattice, double rho, const double *u, double *feq) {
   lat_t L;
-  if (make_lattice(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
+  if (make_model(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
   double v[QMAX];
   equilibrium(&L, rho, u, v);
   for (int i = 0; i < L.Q; ++i) {
@@ -533,35 +691,36 @@ int orc_equilibrium(int32_t lattice, double rho, const double *u, double *feq) {
 int orc_equilibrium_minimiser(int32_t lattice, double rho, const double *u,
                               double *feq, int32_t *iters) {
   lat_t L;
-  if (make_lattice(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
-  int it = equilibrium_minimiser(&L, rho, u, feq);
+  if (make_model(lattice, &L) || !(rho > 0.0) || !u_admissible(&L, u)) return -1;
+  int it = L.ent == ENT_BURG ? equilibrium_burg(&L, rho, u, feq)
+                             : equilibrium_minimiser(&L, rho, u, feq);
   if (iters) *iters = it;
   return it < 0 ? -1 : 0;
 }
 
 int orc_equilibrium_poly(int32_t lattice, double rho, const double *u, double *feq) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return -1;
+  if (make_model(lattice, &L)) return -1;
   equilibrium_poly(&L, rho, u, feq);
   return 0;
 }
 
 int orc_moments_site(int32_t lattice, const double *f, double *rho, double *u) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return -1;
+  if (make_model(lattice, &L)) return -1;
   moments(&L, f, rho, u);
   return 0;
 }
 
 double orc_entropy(int32_t lattice, const double *f) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return NAN;
+  if (make_model(lattice, &L)) return NAN;
   return entropy(&L, f);
 }
 
 double orc_entropy_rel(int32_t lattice, const double *g, const double *feq) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return NAN;
+  if (make_model(lattice, &L)) return NAN;
   double x[QMAX];
   deviations(&L, g, feq, x);
   return Hrel_of(&L, feq, x, 0.0);
@@ -569,13 +728,13 @@ double orc_entropy_rel(int32_t lattice, const double *g, const double *feq) {
 
 double orc_alpha_max(int32_t lattice, const double *f, const double *feq) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return NAN;
+  if (make_model(lattice, &L)) return NAN;
   return alpha_max_of(&L, f, feq);
 }
 
 double orc_G(int32_t lattice, const double *f, double alpha) {
   lat_t L;
-  if (make_lattice(lattice, &L)) return NAN;
+  if (make_model(lattice, &L)) return NAN;
   double rho, u[3], feq[QMAX], x[QMAX];
   moments(&L, f, &rho, u);
   equilibrium(&L, rho, u, feq);

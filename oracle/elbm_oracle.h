@@ -19,6 +19,10 @@
  *   - lattice code 19: D3Q19, the D3Q27 directions with at most two nonzero
  *     components in the order of their D3Q27 index, W = 1/3 (rest),
  *     1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2);
+ *   - entropy: 0 the Boltzmann entropy of Eq. (3), 1 Burg's entropy
+ *     H(f) = -sum_i W_i ln(f_i / W_i) (the paper's formula holds for any
+ *     convex entropy); single-state functions take a model code, the lattice
+ *     code + 256 x entropy;
  *   - populations are SoA: f[i*N + s], s = x + nx*(y + ny*z), x fastest;
  *     velocities are SoA: u[a*N + s].
  *
@@ -52,6 +56,7 @@ typedef struct {
   double root_tol;      /* bisection window -tol <= G <= 0 (paper: 1e-13)     */
   int32_t root_max_iter;/* cap on root-solver iterations                      */
   int32_t nthreads;     /* OpenMP threads for the site loop (1 = serial)      */
+  int32_t entropy;      /* 0 Boltzmann (Eq. (3)), 1 Burg                      */
 } orc_params;
 
 /* Per-site record of how alpha was chosen. */
@@ -82,13 +87,14 @@ typedef struct {
 } orc_diag;
 
 /* ---- lattice and single-state functions -------------------------------- */
-/* The first argument is a lattice code; u has 3 entries (unused ones 0). */
+/* The first argument is a model code (lattice code + 256 x entropy); u has
+ * 3 entries (unused ones 0). */
 int orc_lattice(int32_t lattice, int32_t *Q, int32_t *c /* Q*3 */, double *W);
 /* f^eq: the closed product form (codes 1-3) or the minimiser (code 19);
  * -1 outside the domain (rho <= 0, u outside the velocities' hull). */
 int orc_equilibrium(int32_t lattice, double rho, const double *u, double *feq);
-/* f^eq by Newton's method on the Lagrange multipliers, for any lattice;
- * *iters = Newton iterations. */
+/* f^eq by Newton's method on the Lagrange multipliers, for any lattice and
+ * either entropy; *iters = Newton iterations. */
 int orc_equilibrium_minimiser(int32_t lattice, double rho, const double *u,
                               double *feq, int32_t *iters);
 int orc_equilibrium_poly(int32_t lattice, double rho, const double *u, double *feq);

@@ -24,7 +24,8 @@ class Params(C.Structure):
     _fields_ = [("lattice", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("nz", C.c_int32), ("beta", C.c_double), ("mode", C.c_int32),
                 ("secant_iters", C.c_int32), ("root_tol", C.c_double),
-                ("root_max_iter", C.c_int32), ("nthreads", C.c_int32)]
+                ("root_max_iter", C.c_int32), ("nthreads", C.c_int32),
+                ("entropy", C.c_int32)]
 
 
 class SiteInfo(C.Structure):
@@ -93,15 +94,23 @@ def _f64(a):
 
 # ---------------------------------------------------------------- lattice ---
 # Lattice codes: 1, 2, 3 for the tensor-product lattices D1Q3, D2Q9, D3Q27;
-# 19 for D3Q19.
+# 19 for D3Q19.  Single-state functions take a model code: the lattice code
+# + 256 x entropy (0: the Boltzmann entropy of Eq. (3), 1: Burg's entropy).
 D3Q19 = 19
+ENTROPIES = {"boltzmann": 0, "burg": 1}
+
+
+def model(lat: int, entropy: str = "boltzmann") -> int:
+    return lat + 256 * ENTROPIES[entropy]
 
 
 def lattice_Q(lat: int) -> int:
+    lat &= 255
     return 19 if lat == D3Q19 else 3 ** lat
 
 
 def lattice_D(lat: int) -> int:
+    lat &= 255
     return 3 if lat == D3Q19 else lat
 
 
@@ -177,6 +186,7 @@ class Config:
     root_max_iter: int = 200
     nthreads: int = 1
     q: int = 0            # 0: the tensor-product lattice 3^D; 19: D3Q19 (D = 3)
+    entropy: str = "boltzmann"  # or "burg"
 
     @property
     def lattice(self) -> int:
@@ -187,7 +197,11 @@ class Config:
     def params(self) -> Params:
         return Params(self.lattice, self.nx, self.ny, self.nz, self.beta,
                       MODES[self.mode], self.secant_iters, self.root_tol,
-                      self.root_max_iter, self.nthreads)
+                      self.root_max_iter, self.nthreads, ENTROPIES[self.entropy])
+
+    @property
+    def model(self) -> int:
+        return model(self.lattice, self.entropy)
 
     @property
     def N(self) -> int:

@@ -176,3 +176,111 @@ def near_equilibrium_state(D: int, rho: float, u, eps: float, rng, feq_fn) -> np
     xi = xi - A @ m
     xi /= np.max(np.abs(xi))
     return feq * (1.0 + eps * xi)
+
+
+# ---- Burg's entropy H(f) = -sum_i W_i ln(f_i / W_i) ----------------------
+def burg_equilibrium(D: int, rho: float, u, iters: int = 100) -> np.ndarray:
+    """Minimise Burg's entropy under the mass and momentum constraints by
+    Newton's method on the multipliers of g_i = W_i / (mu . (1, c_i)), with
+    step halving that keeps every mu . (1, c_i) positive (float64).  D is a
+    lattice code."""
+    lat, D = D, dim(D)
+    c = abi_velocities(lat)[:, :D].astype(np.float64)
+    W = textbook_weights(lat)
+    A = np.hstack([np.ones((c.shape[0], 1)), c])
+    b = np.concatenate([[rho], rho * np.asarray(u[:D], dtype=np.float64)])
+    mu = np.zeros(D + 1)
+    mu[0] = 1.0 / rho
+    for _ in range(iters):
+        d = A @ mu
+        r = A.T @ (W / d) - b
+        J = -(A.T @ ((W / d ** 2)[:, None] * A))
+        step = np.linalg.solve(J, r)
+        t = 1.0
+        while np.any(A @ (mu - t * step) <= 0):
+            t *= 0.5
+        mu = mu - t * step
+        if np.max(np.abs(t * step)) < 1e-17:
+            break
+    return W / (A @ mu)
+
+
+def mp_burg_equilibrium(D: int, rho, u, dps: int = 50):
+    """The same minimisation in mpmath arithmetic (list of mpf)."""
+    lat, D = D, dim(D)
+    with mp.workdps(dps):
+        c = abi_velocities(lat)[:, :D]
+        W = mp_weights(lat)
+        Q = len(c)
+        rho = mp.mpf(rho)
+        b = [rho] + [rho * mp.mpf(x) for x in u[:D]]
+        rows = [[mp.mpf(1)] + [mp.mpf(int(c[i, a])) for a in range(D)] for i in range(Q)]
+        mu = [1 / rho] + [mp.mpf(0)] * D
+        for _ in range(200):
+            d = [sum(mu[k] * rows[i][k] for k in range(D + 1)) for i in range(Q)]
+            r = [sum(W[i] * rows[i][k] / d[i] for i in range(Q)) - b[k] for k in range(D + 1)]
+            J = mp.matrix(D + 1, D + 1)
+            for p in range(D + 1):
+                for q in range(D + 1):
+                    J[p, q] = -sum(W[i] * rows[i][p] * rows[i][q] / d[i] ** 2 for i in range(Q))
+            step = mp.lu_solve(J, mp.matrix(r))
+            t = mp.mpf(1)
+            while any(sum((mu[k] - t * step[k]) * rows[i][k] for k in range(D + 1)) <= 0
+                      for i in range(Q)):
+                t /= 2
+            mu = [mu[k] - t * step[k] for k in range(D + 1)]
+            if max(abs(step[k]) for k in range(D + 1)) < mp.mpf(10) ** (-dps + 5):
+                break
+        return [W[i] / sum(mu[k] * rows[i][k] for k in range(D + 1)) for i in range(Q)]
+
+
+def mp_H_burg(f, W) -> mp.mpf:
+    """Burg's entropy in mpmath: -sum W ln(f/W); +inf at a zero population."""
+    h = mp.mpf(0)
+    for fi, wi in zip(f, W):
+        fi = mp.mpf(fi)
+        if fi < 0:
+            raise ValueError("negative population")
+        if fi == 0:
+            return mp.inf
+        h -= wi * mp.log(fi / wi)
+    return h
+
+
+def _mp_state_burg(D, f, dps):
+    fm = [mp.mpf(float(v)) for v in f]
+    rho = sum(fm)
+    c = abi_velocities(D)
+    u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(dim(D))]
+    return fm, mp_burg_equilibrium(D, rho, u, dps), mp_weights(D)
+
+
+def mp_G_burg(D: int, f, alpha, dps: int = 50) -> mp.mpf:
+    """H(f + alpha (f^eq - f)) - H(f) for Burg's entropy, all in mpmath."""
+    with mp.workdps(dps):
+        fm, feq, W = _mp_state_burg(D, f, dps)
+        a = mp.mpf(float(alpha))
+        fs = [fm[i] + a * (feq[i] - fm[i]) for i in range(len(fm))]
+        return mp_H_burg(fs, W) - mp_H_burg(fm, W)
+
+
+def mp_root_burg(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
+    """Nontrivial root of Burg's G on [lo, hi] by mpmath bisection."""
+    with mp.workdps(dps):
+        fm, feq, W = _mp_state_burg(D, f, dps)
+        H0 = mp_H_burg(fm, W)
+
+        def G(a):
+            fs = [fm[i] + a * (feq[i] - fm[i]) for i in range(len(fm))]
+            if min(fs) <= 0:
+                return mp.inf
+            return mp_H_burg(fs, W) - H0
+
+        lo, hi = mp.mpf(lo), mp.mpf(hi)
+        for _ in range(iters):
+            mid = (lo + hi) / 2
+            if G(mid) > 0:
+                hi = mid
+            else:
+                lo = mid
+        return lo
