@@ -104,6 +104,18 @@ enum {
   ELBM_STORE_F16_DEV = 3
 };
 
+/* Entropy function.  The paper states the scheme for the Boltzmann entropy
+ * of Eq. (3) and remarks that the closed form (Eq. (9)) needs only a convex
+ * entropy; the library also runs it with Burg's entropy
+ *   H(f) = -sum_i W_i ln(f_i / W_i),
+ * whose equilibrium f_i = W_i / (m0 + m.c_i) is found per site by Newton's
+ * method on the multipliers (no closed form on any lattice).  Burg's entropy
+ * is infinite at a zero population, so alpha_* = alpha_max < 2 gives
+ * alpha = 1 (the limit of Eq. (9)).  Burg is built for the entropic alpha
+ * modes (not LBGK, which uses no entropy), FP64 arithmetic, FP64 and FP32
+ * storage. */
+enum { ELBM_ENTROPY_BOLTZMANN = 0, ELBM_ENTROPY_BURG = 1 };
+
 /* Diagnostics switches (bit mask). */
 enum {
   ELBM_DIAG_ALPHA = 1u,  /* record alpha(x) of every step (8 B/site extra) */
@@ -126,7 +138,8 @@ typedef struct {
   double root_tol;       /* bisection window; the paper uses 1e-13        */
   int32_t root_max_iter; /* cap for Newton / bisection iterations (>= 1)  */
   uint32_t diag;         /* ELBM_DIAG_* mask                              */
-  int32_t reserved[2];   /* must be 0                                     */
+  int32_t entropy;       /* ELBM_ENTROPY_*                                */
+  int32_t reserved;      /* must be 0                                     */
 } elbm_config;
 
 /* Per-step diagnostics of the most recent step (ELBM_DIAG_COUNTS).  In

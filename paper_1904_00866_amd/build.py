@@ -21,8 +21,10 @@ LIB = os.path.join(HERE, "libelbm.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 SOURCES = ["elbm_step_d1.hip", "elbm_step_d2.hip", "elbm_step_d3.hip", "elbm_step_q19.hip",
+           "elbm_step_burg.hip",
            "elbm_aux.hip", "elbm_api.cpp", "elbm_serve.cpp"]
-HEADERS = ["elbm_site.hpp", "elbm_internal.hpp", "elbm_step_impl.hpp", "elbm_q19.hpp"]
+HEADERS = ["elbm_site.hpp", "elbm_internal.hpp", "elbm_step_impl.hpp", "elbm_q19.hpp",
+           "elbm_burg.hpp"]
 
 
 def hipcc() -> str:

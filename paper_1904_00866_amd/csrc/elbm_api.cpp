@@ -95,9 +95,13 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   if (c->diag & ~7u) return fail(ELBM_EINVAL, "unknown diagnostics bits 0x%x", c->diag);
   if ((c->diag & ELBM_DIAG_SUMS) && !(c->diag & ELBM_DIAG_COUNTS))
     return fail(ELBM_EINVAL, "ELBM_DIAG_SUMS needs ELBM_DIAG_COUNTS");
-  if (c->reserved[0] != 0 || c->reserved[1] != 0) return fail(ELBM_EINVAL, "reserved must be 0");
-  if (!step_launcher(c->lattice, c->storage, c->alpha_mode, c->alpha_fp64))
-    return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision");
+  if (c->reserved != 0) return fail(ELBM_EINVAL, "reserved must be 0");
+  if (c->entropy != ELBM_ENTROPY_BOLTZMANN && c->entropy != ELBM_ENTROPY_BURG)
+    return fail(ELBM_EINVAL, "unknown entropy %d", c->entropy);
+  if (c->entropy == ELBM_ENTROPY_BURG && c->alpha_mode == ELBM_ALPHA_BGK)
+    return fail(ELBM_EUNSUPPORTED, "LBGK uses no entropy function: use ELBM_ENTROPY_BOLTZMANN");
+  if (!step_launcher(c->lattice, c->storage, c->alpha_mode, c->alpha_fp64, c->entropy))
+    return fail(ELBM_EUNSUPPORTED, "no kernel for this lattice/storage/mode/precision/entropy");
 
   L->lattice = c->lattice;
   L->D = D;
@@ -179,6 +183,7 @@ BoxDesc box_of(const elbm_sim* s) {
   BoxDesc b;
   b.lattice = s->L.lattice;
   b.D = s->L.D;
+  b.entropy = s->cfg.entropy;
   b.storage = s->cfg.storage;
   b.nx = s->cfg.nx;
   b.ny = s->cfg.ny;
@@ -316,7 +321,8 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
   s->device = dev;
   s->t = 0;
   s->have_alpha = s->have_stats = false;
-  s->launch = step_launcher(cfg->lattice, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64);
+  s->launch = step_launcher(cfg->lattice, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64,
+                            cfg->entropy);
 
   const BoxDesc b = box_of(s);
   unsigned long long nbad = 0;
@@ -389,8 +395,9 @@ elbm_status elbm_step_batch(elbm_sim* const* sims, const int64_t* nsteps, int32_
     if (!s) return fail(ELBM_EINVAL, "batch entry %d is NULL", k);
     if (nsteps[k] < 0) return fail(ELBM_EINVAL, "batch entry %d: nsteps < 0", k);
     if (s->L.lattice != s0->L.lattice || s->cfg.storage != s0->cfg.storage ||
-        s->cfg.alpha_mode != s0->cfg.alpha_mode || s->cfg.alpha_fp64 != s0->cfg.alpha_fp64)
-      return fail(ELBM_EINVAL, "batch entry %d: lattice/storage/mode/precision differ", k);
+        s->cfg.alpha_mode != s0->cfg.alpha_mode || s->cfg.alpha_fp64 != s0->cfg.alpha_fp64 ||
+        s->cfg.entropy != s0->cfg.entropy)
+      return fail(ELBM_EINVAL, "batch entry %d: lattice/storage/mode/precision/entropy differ", k);
     if (s->stream != s0->stream || s->device != s0->device)
       return fail(ELBM_EINVAL, "batch entry %d: different stream or device", k);
     for (int32_t m = 0; m < k; ++m)

@@ -6,6 +6,7 @@
 // P_i(x - c_i) = f_i(x, t), i.e. the post-collision values of the previous
 // step before streaming (Eq. (5b) is carried out by the reader).
 #include "elbm_internal.hpp"
+#include "elbm_burg.hpp"
 #include "elbm_q19.hpp"
 #include "elbm_site.hpp"
 
@@ -71,7 +72,13 @@ __global__ void k_scatter(const BoxDesc b, typename S::T* __restrict__ buf,
   if (which == 0) {
     double u[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < D; ++a) u[a] = u0[a * b.N + s];
-    if constexpr (Q == 19) {
+    if (b.entropy == 1) {
+      // Burg's entropy: f^eq_i = W_i / d_i (elbm_burg.hpp)
+      double mu[4];
+      burg_multipliers<L>(rho0[s], 1.0 / rho0[s], u, mu);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) fv[i] = L::W(i) / burg_den<L>(mu, i);
+    } else if constexpr (Q == 19) {
       // f^eq_i = rho W_i prod_a X_a^c_ia / Z  (EquilibriumQ19)
       EquilibriumQ19<double> eq;
       eq.build(u);
@@ -284,7 +291,9 @@ hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_
   return hipGetLastError();
 }
 
-StepLauncher step_launcher(int lattice, int storage, int mode, int fp64) {
+StepLauncher step_launcher(int lattice, int storage, int mode, int fp64, int entropy) {
+  if (entropy == 1) return step_launcher_burg(lattice, storage, mode, fp64);
+  if (entropy != 0) return nullptr;
   switch (lattice) {
     case 1: return step_launcher_d1(storage, mode, fp64);
     case 2: return step_launcher_d2(storage, mode, fp64);

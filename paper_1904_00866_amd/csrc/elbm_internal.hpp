@@ -96,16 +96,18 @@ struct Reduced {
 // Launchers (defined in the kernel translation units).  Each returns the
 // hipError_t of its launch.
 using StepLauncher = hipError_t (*)(const BatchArgs&, int grid, hipStream_t);
-// lattice: 1, 2, 3 (D1Q3, D2Q9, D3Q27) or 19 (D3Q19)
-StepLauncher step_launcher(int lattice, int storage, int mode, int fp64);
+// lattice: 1, 2, 3 (D1Q3, D2Q9, D3Q27) or 19 (D3Q19); entropy: 0 Boltzmann, 1 Burg
+StepLauncher step_launcher(int lattice, int storage, int mode, int fp64, int entropy);
 StepLauncher step_launcher_d1(int storage, int mode, int fp64);
 StepLauncher step_launcher_d2(int storage, int mode, int fp64);
 StepLauncher step_launcher_d3(int storage, int mode, int fp64);
 StepLauncher step_launcher_q19(int storage, int mode, int fp64);
+StepLauncher step_launcher_burg(int lattice, int storage, int mode, int fp64);
 
 // Auxiliary kernels: a population buffer `buf` in the layout of pidx().
 struct BoxDesc {
   int lattice, D, storage;
+  int entropy;  // 0 Boltzmann, 1 Burg (the equilibrium that init places)
   int32_t nx, ny, nz;
   int64_t N, padded;
   double rho_ref;

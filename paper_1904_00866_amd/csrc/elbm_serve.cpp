@@ -185,8 +185,10 @@ void recycle_pinned(elbm_server* s, Pinned p) {
 }
 
 bool group_less(const Req* a, const Req* b) {
-  return std::make_tuple(a->cfg.lattice, a->cfg.storage, a->cfg.alpha_mode, a->cfg.alpha_fp64) <
-         std::make_tuple(b->cfg.lattice, b->cfg.storage, b->cfg.alpha_mode, b->cfg.alpha_fp64);
+  return std::make_tuple(a->cfg.lattice, a->cfg.storage, a->cfg.alpha_mode, a->cfg.alpha_fp64,
+                         a->cfg.entropy) <
+         std::make_tuple(b->cfg.lattice, b->cfg.storage, b->cfg.alpha_mode, b->cfg.alpha_fp64,
+                         b->cfg.entropy);
 }
 
 bool same_group(const Req* a, const Req* b) { return !group_less(a, b) && !group_less(b, a); }

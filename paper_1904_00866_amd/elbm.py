@@ -27,6 +27,7 @@ def lattice_dq(code: int):
 MODES = {"closed": 0, "newton": 1, "bisect": 2, "bgk": 3, "secant": 4}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 DIAG_ALPHA, DIAG_COUNTS, DIAG_SUMS = 1, 2, 4
+ENTROPIES = {"boltzmann": 0, "burg": 1}
 STATUS = {0: "ELBM_OK", -1: "ELBM_EINVAL", -2: "ELBM_EDEVICE", -3: "ELBM_ENOMEM",
           -4: "ELBM_ESTATE", -5: "ELBM_EUNSUPPORTED"}
 EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_populations",
@@ -51,7 +52,7 @@ class Config(C.Structure):
                 ("storage", C.c_int32), ("alpha_fp64", C.c_int32),
                 ("secant_iters", C.c_int32), ("rho_ref", C.c_double),
                 ("root_tol", C.c_double), ("root_max_iter", C.c_int32),
-                ("diag", C.c_uint32), ("reserved", C.c_int32 * 2)]
+                ("diag", C.c_uint32), ("entropy", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -145,7 +146,7 @@ def _check(rc: int):
 
 def make_config(lattice, nx, ny=1, nz=1, *, beta=0.95, mode="closed", storage="f32",
                 fp64=True, secant_iters=3, rho_ref=1.0, root_tol=1e-13,
-                root_max_iter=200, diag=0) -> Config:
+                root_max_iter=200, diag=0, entropy="boltzmann") -> Config:
     cfg = Config()
     lat = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     _check(lib().elbm_config_default(C.byref(cfg), lat, nx, ny, nz))
@@ -158,6 +159,7 @@ def make_config(lattice, nx, ny=1, nz=1, *, beta=0.95, mode="closed", storage="f
     cfg.root_tol = float(root_tol)
     cfg.root_max_iter = int(root_max_iter)
     cfg.diag = int(diag)
+    cfg.entropy = ENTROPIES[entropy] if isinstance(entropy, str) else int(entropy)
     return cfg
 
 

@@ -87,6 +87,32 @@ def test_d3q19_config_and_state_bytes():
             elbm.state_bytes(c)
 
 
+def test_burg_entropy_configs():
+    """Burg's entropy is built for the entropic alpha modes with FP64
+    arithmetic and FP64 / FP32 storage on every lattice; LBGK (no entropy),
+    deviation storage and FP32 arithmetic are refused, unknown entropies are
+    invalid."""
+    for lat in ("d1q3", "d2q9", "d3q27", "d3q19"):
+        shape = {"d1q3": (64, 1, 1), "d2q9": (16, 16, 1)}.get(lat, (8, 8, 8))
+        for mode in ("closed", "newton", "bisect", "secant"):
+            for storage in ("f64", "f32"):
+                cfg = elbm.make_config(lat, *shape, mode=mode, storage=storage, entropy="burg")
+                assert elbm.state_bytes(cfg) > 0
+    # elbm_state_bytes returns 0 and sets the message (the status of the
+    # configuration check is in the message's wording)
+    for kw, msg in [(dict(mode="bgk"), "LBGK uses no entropy"), (dict(storage="f16dev"), "no kernel"),
+                    (dict(storage="f32dev"), "no kernel"), (dict(fp64=False), "no kernel"),
+                    (dict(entropy=2), "unknown entropy")]:
+        args = dict(entropy="burg")
+        args.update(kw)
+        with pytest.raises(elbm.ElbmError, match=msg):
+            elbm.state_bytes(elbm.make_config("d2q9", 16, 16, **args))
+    c = elbm.make_config("d2q9", 16, 16)
+    c.reserved = 1
+    with pytest.raises(elbm.ElbmError, match="reserved"):
+        elbm.state_bytes(c)
+
+
 def test_large_boxes_fit_the_layout():
     """A 1024^3 FP32 D3Q27 state (232 GB with both buffers) is a valid
     configuration: the blocked layout has no per-buffer size limit."""
