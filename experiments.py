@@ -19,6 +19,11 @@ is needed; its parity with the CPU oracle is established by the GPU tests).
                                  and (256^3) Newton; 128^3 Re = 1600 Taylor-Green:
                                  kinetic-energy decay and the share of sites
                                  with alpha < 2 on both lattices
+    python experiments.py f3burg Burg's entropy beside the Boltzmann entropy
+                                 (closed form, FP32 storage): step time and HBM
+                                 fraction at D3Q27 512^3 and D2Q9 2048^2, Newton
+                                 at 256^3; 128^3 Re = 1600 Taylor-Green: kinetic
+                                 energy and the share of sites with alpha < 2
 Each prints one JSON object per experiment on stdout.
 """
 from __future__ import annotations
@@ -318,15 +323,86 @@ def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
     return out
 
 
+def f3burg(n3=512, n2=2048, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000,
+           copy_mib=0, cases=None):
+    out = {"experiment": "f3burg", "workload": f"Taylor-Green (u0 = 0.05, Re = 1600), FP32 "
+           f"storage, FP64 site arithmetic, closed-form alpha unless noted: D3Q27 {n3}^3, "
+           f"D2Q9 {n2}^2, Newton at {newton_n}^3; {steps} timed steps after 3 warm-up; "
+           f"Taylor-Green {tgv_n}^3 over {tgv_steps} steps", "timing": {}, "tgv": {}}
+    if copy_mib:
+        a = torch.empty(copy_mib << 18, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    all_cases = [("d3q27", n3, "closed", "burg"), ("d3q27", n3, "closed", "boltzmann"),
+                 ("d2q9", n2, "closed", "burg"), ("d2q9", n2, "closed", "boltzmann"),
+                 ("d3q27", newton_n, "newton", "burg")]
+    for lat, m, mode, ent in all_cases:
+        if cases and f"{lat}_{mode}_{ent}" not in cases:
+            continue
+        Q = 27 if lat == "d3q27" else 9
+        if lat == "d3q27":
+            rho, u = Wk.taylor_green_3d(m)
+            shape, beta = (m, m, m), Wk.tgv3d_beta(m)
+        else:
+            rho, u = Wk.taylor_green_2d(m)
+            shape, beta = (m, m, 1), Wk.beta_from_nu(0.05 * m / (2.0 * math.pi) / 1600.0)
+        N = int(np.prod(shape))
+        with elbm.Simulation(lat, *shape, rho0=rho, u0=u, storage="f32", mode=mode, beta=beta,
+                             entropy=ent) as sim:
+            del rho, u
+            sim.step(3)
+            ms = _timed_steps(sim, steps if mode != "newton" else 3)
+        gbs = 2.0 * Q * 4 * N / (ms * 1e-3) / 1e9
+        key = f"{lat}_{mode}_{ent}"
+        out["timing"][key] = {"n": m, "ms_per_step": round(ms, 4),
+                              "mlups": round(N / (ms * 1e-3) / 1e6, 1),
+                              "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"f3burg {key}: {out['timing'][key]}")
+        torch.cuda.empty_cache()
+    for ent in ("burg", "boltzmann") if tgv_steps > 0 else ():
+        m = tgv_n
+        rho, u = Wk.taylor_green_3d(m)
+        rec = []
+        with elbm.Simulation("d3q27", m, m, m, rho0=rho, u0=u, storage="f32",
+                             beta=Wk.tgv3d_beta(m), diag=elbm.DIAG_COUNTS, entropy=ent) as sim:
+            r, v = sim.moments()
+            ke0 = _kinetic(r, v)
+            for t in range(250, tgv_steps + 1, 250):
+                sim.step(249)
+                sim.step(1)
+                st = sim.stats()
+                r, v = sim.moments()
+                torch.cuda.synchronize()
+                rec.append({"t": t, "ke_ratio": _kinetic(r, v) / ke0,
+                            "alpha_lt2_frac": st["n_alpha_lt2"] / st["n_sites"],
+                            "alpha_min": st["alpha_min"],
+                            "alphastar_lt2": st["n_alphastar_lt2"]})
+        out["tgv"][ent] = rec
+        log(f"f3burg tgv {ent}: {rec[-1]}")
+    T = out["timing"]
+    for lat in ("d3q27", "d2q9"):
+        a, b = T.get(f"{lat}_closed_burg"), T.get(f"{lat}_closed_boltzmann")
+        if a and b:
+            out[f"{lat}_burg_over_boltzmann_time"] = round(a["ms_per_step"] / b["ms_per_step"], 3)
+    if "d3q27_closed_burg" in T and "d3q27_newton_burg" in T:
+        out["burg_closed_over_newton"] = round(
+            T["d3q27_closed_burg"]["mlups"] / T["d3q27_newton_burg"]["mlups"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "f3"])
+    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "f3", "f3burg"])
     ap.add_argument("--w2-steps", type=int, default=20000)
     ap.add_argument("--f3-n", type=int, default=512)
     ap.add_argument("--f3-steps", type=int, default=20)
     ap.add_argument("--f3-tgv-steps", type=int, default=2000)
     ap.add_argument("--f3-modes", default="closed,bgk,newton")
     ap.add_argument("--f3-lattices", default="d3q19,d3q27")
+    ap.add_argument("--f3burg-cases", default="",
+                    help="comma list of lattice_mode_entropy cases (default: all)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one torch copy of this many MiB first (HBM counter scale)")
     args = ap.parse_args()
@@ -337,6 +413,9 @@ def main():
     for w in args.which:
         t0 = time.time()
         res = {"w1": w1, "e2": e2, "w4": w4,
+               "f3burg": lambda: f3burg(n3=args.f3_n, steps=args.f3_steps,
+                                        tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
+                                        cases=[c for c in args.f3burg_cases.split(",") if c]),
                "f3": lambda: f3(n=args.f3_n, steps=args.f3_steps,
                                 tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
                                 modes=tuple(args.f3_modes.split(",")),
