@@ -101,22 +101,15 @@ struct Codec {
 // -------------------------------------------------------------- precision --
 template <class R>
 struct Prec;
+// guard: f = f^eq to rounding when H(f) - H(f^eq) <= guard * rho.
 template <>
 struct Prec<double> {
-  // Series lengths K1 < K2 < K3 and the largest max_i |x_i| (thr1..thr3) for
-  // which each leaves an alpha error below 2^-53: truncating E and O after K
-  // terms changes alpha by about 2 x^(2K+1) / ((2K+3)(2K+2)).
-  static constexpr int K1 = 4, K2 = 8, K3 = 14;
-  static constexpr double thr1 = 0.025, thr2 = 0.15, thr3 = 0.30;
   static constexpr double guard = 1e-26;
   __device__ static __forceinline__ double log1p_(double y) { return ::log1p(y); }
   __device__ static __forceinline__ double sqrt_(double y) { return ::sqrt(y); }
 };
 template <>
 struct Prec<float> {
-  // Same bound at 2^-24.
-  static constexpr int K1 = 2, K2 = 4, K3 = 7;
-  static constexpr float thr1 = 0.06f, thr2 = 0.24f, thr3 = 0.30f;
   static constexpr float guard = 1e-30f;
   __device__ static __forceinline__ float log1p_(float y) { return ::log1pf(y); }
   __device__ static __forceinline__ float sqrt_(float y) { return ::sqrtf(y); }
@@ -260,22 +253,7 @@ struct SeriesK {
                            (1.0 / ((2.0 * K + 1.0) * (2.0 * K)))));
     }
   }
-  __device__ __forceinline__ void eval(R x, R& E, R& O) const {
-    const R t = x * x;
-    R pe = R(1), po = R(1);
-    if constexpr (K >= 2) {
-      pe = t + e[K - 2];
-      po = t + o[K - 2];
-    }
-#pragma unroll
-    for (int k = K - 2; k >= 1; --k) {
-      pe = fma(pe, t, e[k - 1]);
-      po = fma(po, t, o[k - 1]);
-    }
-    E = pe * t;
-    O = po * t * x;
-  }
-  // sE += f E(x), sO += f O(x), the K-term sums scaled as for eval(), with
+  // sE += f E(x), sO += f O(x), the K-term sums scaled by 1/c_K, 1/d_K, with
   // f x^2 formed once for both: one multiplication fewer per direction.
   __device__ __forceinline__ void accum(R x, R f, R& sE, R& sO) const {
     const R t = x * x;
@@ -295,12 +273,7 @@ struct SeriesK {
   }
 };
 
-template <class R, int K>
-__device__ __forceinline__ void series_EO(R x, R& E, R& O) {
-  SeriesK<R, K>().eval(x, E, O);
-}
-
-// (c_K, d_K): the factors that restore series_EO's sums.
+// (c_K, d_K): the factors that restore the sums of SeriesK.
 template <class R, int K>
 __device__ __forceinline__ void series_scale(R& cE, R& cO) {
   cE = R(1.0 / ((2.0 * K) * (2.0 * K - 1.0)));
