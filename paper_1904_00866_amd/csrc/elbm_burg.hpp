@@ -5,9 +5,36 @@
 // the Lagrangian makes h'(f^eq_i) = -W_i / f^eq_i affine in (1, c_i)).
 #pragma once
 
+#include "elbm_q19.hpp"
 #include "elbm_site.hpp"
 
 namespace elbm {
+
+// Direction index of the digits (dx, dy, dz) on lattice L, or -1 if L has
+// no such direction.
+template <class L>
+struct Dirs;
+template <int D>
+struct Dirs<Lattice<D>> {
+  static constexpr int index(int dx, int dy, int dz) {
+    return ((D < 2 && dy != 0) || (D < 3 && dz != 0)) ? -1 : dx + 3 * dy + 9 * dz;
+  }
+};
+template <>
+struct Dirs<LatticeQ19> {
+  static constexpr int index(int dx, int dy, int dz) {
+    return (dx != 0 && dy != 0 && dz != 0)
+               ? -1
+               : (dx + 3 * dy + 9 * dz) - 2 * ((dx + 3 * dy + 9 * dz) >= 13) -
+                     2 * ((dx + 3 * dy + 9 * dz) >= 18) - 2 * ((dx + 3 * dy + 9 * dz) >= 22);
+  }
+};
+
+// Index of the direction -c_i (digits 1 and 2 swapped).
+template <class L>
+constexpr int opposite(int i) {
+  return Dirs<L>::index((3 - L::dg(i, 0)) % 3, (3 - L::dg(i, 1)) % 3, (3 - L::dg(i, 2)) % 3);
+}
 
 template <class L>
 __device__ __forceinline__ double burg_den(const double (&mu)[4], int i) {
@@ -63,13 +90,15 @@ __device__ __forceinline__ void ldl_solve(const double (&S)[4][4], const double 
 //   g(mu) = sum_i W_i ln(d_i) - mu.b,   b = (rho, rho u),
 // whose gradient F(mu) = sum_i W_i a_i / d_i - b (a_i = (1, c_i)) is the
 // constraint residual and whose Hessian is -S, S = sum_i W_i a_i a_i^T / d_i^2.
-// Newton's method mu <- mu + t S^-1 F from the second-order solution
-// mu = ((1 + 3 u.u) / rho, -3 u / rho), its velocity part scaled down where
-// that would leave some d_i below mu_0 / 2 (the constraint equations have
-// other roots, with negative populations, outside d > 0).  t is halved while
-// a step would make some d_i non-positive or, for a step above 5 % of mu_0,
-// fail to increase g (Armijo); small steps near the solution take t = 1 and
-// no logarithms.  Stops after a step below 1e-9 mu_0 (quadratic convergence
+// Newton's method mu <- mu + t S^-1 F from the third-order solution
+// mu = ((1 + 3 u.u) / rho, -3 u (1 - 3 u.u) / rho) (expanding the constraints
+// with the lattices' isotropic moments up to fourth order), its velocity part
+// scaled down where that would leave some d_i below mu_0 / 2 (the constraint
+// equations have other roots, with negative populations, outside d > 0).
+// t is halved while a step would make some d_i non-positive or, for a step
+// above 5 % of mu_0, fail to increase g (Armijo); a step whose (D+1) max|z|
+// is below min_i d_i keeps every d_i positive, and small steps near the
+// solution take t = 1 with neither check.  Stops after a step below 1e-9 mu_0 (quadratic convergence
 // leaves an error of order its square), at most 32 iterations.
 template <class L>
 __device__ __forceinline__ double burg_dual(const double (&mu)[4], double rho, const double (&u)[3]) {
@@ -89,8 +118,9 @@ __device__ __forceinline__ void burg_multipliers(double rho, double irho, const 
 #pragma unroll
   for (int a = 0; a < D; ++a) uu += u[a] * u[a];
   mu[0] = (1.0 + 3.0 * uu) * irho;
+  const double sv = -3.0 * (1.0 - 3.0 * uu) * irho;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) mu[a + 1] = a < D ? -3.0 * u[a] * irho : 0.0;
+  for (int a = 0; a < 3; ++a) mu[a + 1] = a < D ? sv * u[a] : 0.0;
   double dmin = INFINITY;
 #pragma unroll
   for (int i = 0; i < Q; ++i) dmin = fmin(dmin, burg_den<L>(mu, i));
@@ -107,17 +137,49 @@ __device__ __forceinline__ void burg_multipliers(double rho, double irho, const 
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int m = 0; m < 4; ++m) Sm[k][m] = 0.0;
+      // Directions in pairs (c, -c) with W_-c = W_c: d_+- = mu_0 +- v,
+      // v = sum_a c_a mu_a; one reciprocal of d_+ d_- gives both 1/d_+-, and
+      // the pair adds W (r_+ + r_-) a a^T-even and W (r_+ - r_-) odd terms.
+      double dlo = INFINITY;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double r = rcp_n<double>(burg_den<L>(mu, i));
-        const double w = L::W(i) * r, w2 = w * r;
-        double a[4] = {1.0, double(L::c(i, 0)), double(L::c(i, 1)), double(L::c(i, 2))};
+        const int io = opposite<L>(i);
+        if (io < i) continue;  // the pair was taken at io
+        double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-          if (a[k] != 0.0) F[k] += a[k] * w;
+        for (int a = 0; a < D; ++a) {
+          const int c = L::c(i, a);
+          if (c > 0) v += mu[a + 1];
+          else if (c < 0) v -= mu[a + 1];
+        }
+        const double W = L::W(i);
+        if (io == i) {  // the rest direction: a = (1, 0, ...)
+          const double r = rcp_n<double>(mu[0]);
+          dlo = fmin(dlo, mu[0]);
+          F[0] += W * r;
+          Sm[0][0] += W * r * r;
+          continue;
+        }
+        const double dp = mu[0] + v, dm = mu[0] - v;
+        dlo = fmin(dlo, fmin(dp, dm));
+        const double rp2 = rcp_n<double>(dp * dm);
+        const double rp = dm * rp2, rm = dp * rp2;
+        const double ev = W * (rp + rm), od = W * (rp - rm);
+        const double ev2 = W * fma(rp, rp, rm * rm), od2 = W * ((rp + rm) * (rp - rm));
+        F[0] += ev;
+        Sm[0][0] += ev2;
 #pragma unroll
-          for (int m = k; m < N; ++m)
-            if (a[k] * a[m] != 0.0) Sm[k][m] += (a[k] * a[m]) * w2;
+        for (int k = 1; k < N; ++k) {
+          const int ck = L::c(i, k - 1);
+          if (ck == 0) continue;
+          F[k] += ck > 0 ? od : -od;
+          Sm[0][k] += ck > 0 ? od2 : -od2;
+#pragma unroll
+          for (int m = k; m < N; ++m) {
+            const int cm = L::c(i, m - 1);
+            if (cm == 0) continue;
+            Sm[k][m] += ck * cm > 0 ? ev2 : -ev2;
+          }
         }
       }
       F[0] -= rho;
@@ -134,7 +196,9 @@ __device__ __forceinline__ void burg_multipliers(double rho, double irho, const 
       const bool big = zmax > 0.05 * mu[0];
       const double g0 = big ? burg_dual<L>(mu, rho, u) : 0.0;
       double t = 1.0;
-      for (int h = 0; h < 12; ++h) {
+      // |change of d_i| <= (D + 1) max|z|: below min d_i no d_i can turn
+      const bool safe = !big && double(N) * zmax < dlo;
+      for (int h = 0; h < (safe ? 0 : 12); ++h) {
         double mt[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) mt[k] = k < N ? mu[k] + t * z[k] : 0.0;

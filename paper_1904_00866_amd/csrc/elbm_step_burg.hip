@@ -28,26 +28,6 @@
 namespace elbm {
 namespace {
 
-// Direction index of the digits (dx, dy, dz) on lattice L, or -1 if L has
-// no such direction.
-template <class L>
-struct Dirs;
-template <int D>
-struct Dirs<Lattice<D>> {
-  static constexpr int index(int dx, int dy, int dz) {
-    return ((D < 2 && dy != 0) || (D < 3 && dz != 0)) ? -1 : dx + 3 * dy + 9 * dz;
-  }
-};
-template <>
-struct Dirs<LatticeQ19> {
-  static constexpr int index(int dx, int dy, int dz) {
-    return (dx != 0 && dy != 0 && dz != 0)
-               ? -1
-               : (dx + 3 * dy + 9 * dz) - 2 * ((dx + 3 * dy + 9 * dz) >= 13) -
-                     2 * ((dx + 3 * dy + 9 * dz) >= 18) - 2 * ((dx + 3 * dy + 9 * dz) >= 22);
-  }
-};
-
 // Pull of the Q populations when the wavefront's 64 sites lie in one x-row
 // (one descriptor per source row (c_y, c_z); see load_site_row).
 template <class L, class T>
@@ -367,7 +347,8 @@ __global__ void __launch_bounds__(kBlock) k_step_burg(const BatchArgs args) {
   } else if (!(diag & kDiagCounts)) {
     return;  // padding workgroup
   }
-  if (diag & kDiagCounts) store_records<true>(acc, d, (int)lb);
+  // iterations are recorded for the secant and the root solvers, as in k_step
+  if (diag & kDiagCounts) store_records<MODE != kClosed>(acc, d, (int)lb);
 }
 
 template <class L, class S, int MODE>
