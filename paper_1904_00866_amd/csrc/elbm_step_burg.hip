@@ -9,7 +9,7 @@
 //   - equilibrium: stationarity gives W_i / f^eq_i = m0 + m.c_i, so
 //     f^eq_i = W_i / d_i with d_i = mu . (1, c_i); the D + 1 multipliers mu
 //     solve the mass and momentum constraints, found per site by Newton's
-//     method from the first-order solution mu = (1/rho, -3u/rho);
+//     method (elbm_burg.hpp);
 //   - x_i = g_i / f^eq_i - 1 = g_i d_i / W_i - 1 needs no reciprocal;
 //   - entropy differences between states with the moments of f^eq are the
 //     exact relative form H(g) - H(f^eq) = sum_i W_i chi(g_i / f^eq_i - 1),

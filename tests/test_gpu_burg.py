@@ -4,7 +4,7 @@ every lattice.
 
 The equilibrium (f^eq_i = W_i / (m0 + m.c_i)) is found per site by Newton's
 method on the multipliers on both sides, by independent solvers (GPU: from
-the second-order solution kept inside d > 0, Armijo steps only for long
+the third-order solution kept inside d > 0, Armijo steps only for long
 steps; oracle: from the rest state, Armijo steps throughout).  Tolerances as
 for the Boltzmann entropy: FP64 storage 1e-13 per population for one step,
 1e-11 over a run; FP32 storage one rounding of the output.
