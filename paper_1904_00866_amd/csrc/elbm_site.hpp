@@ -72,15 +72,34 @@ struct StoreF16Dev {
   static constexpr bool dev = true;
 };
 
+// What a site keeps of each loaded population between its passes: the
+// stored value, except for FP16 deviations, which are kept converted to FP32
+// (exactly), so that each pass needs one widening instead of two.
+template <class S>
+struct Kept {
+  using type = typename S::T;
+};
+template <>
+struct Kept<StoreF16Dev> {
+  using type = float;
+};
+
 template <class S, class R>
 struct Codec {
+  static constexpr bool kF16 = S::dev && sizeof(typename S::T) == 2;
+  // decoded population f = W (rho_ref + s) (deviation formats), formed as
+  // W s + W rho_ref with one rounding; or the stored value
   __device__ static __forceinline__ R dec(typename S::T v, R W, R rho_ref) {
-    if constexpr (S::dev) return W * (rho_ref + (R)v);
+    if constexpr (S::dev) return fma(W, (R)v, W * rho_ref);
     else return (R)v;
   }
-  // the same from a value already widened to R
+  __device__ static __forceinline__ typename Kept<S>::type keep(typename S::T v) {
+    if constexpr (kF16) return (float)v;
+    else return v;
+  }
+  // decode of a kept value already widened to R (the same arithmetic as dec)
   __device__ static __forceinline__ R dec_wide(R v, R W, R rho_ref) {
-    if constexpr (S::dev) return W * (rho_ref + v);
+    if constexpr (S::dev) return fma(W, v, W * rho_ref);
     else return v;
   }
   // FP16 is formed from the FP32 value (there is no direct FP64 -> FP16

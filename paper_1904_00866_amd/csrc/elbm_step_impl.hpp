@@ -233,7 +233,7 @@ struct Site {
   static constexpr int kDim = D;
   // f^eq_i = f01[dx][dy] e2[dz]: the common tier sums over c_z per (c_x, c_y)
   static constexpr bool kZFactor = (D == 3);
-  T raw[Q];
+  typename Kept<S>::type raw[Q];  // the loaded populations as kept (Kept<S>)
   R rho, irho, rho_ref;
   R u[3];
   // With e[a][d] = w(c) A_a z_a^c (digit d of c) and ie[a][d] = 1/e[a][d]
@@ -948,7 +948,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
 
   Site<D, S, R> v;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v.raw[i] = raw[i];
+  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
   R rho, j[3];
   site_prepare(v, d, src, sl, rho, j, MODE != kBGK);
   const R beta = (R)d.beta;
@@ -1029,7 +1029,14 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;
   Site<D, S, R> v;
-  load_site<D>(d, src, sl, v.raw);
+  if constexpr (Codec<S, R>::kF16) {
+    T raw[Q];
+    load_site<D>(d, src, sl, raw);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
+  } else {
+    load_site<D>(d, src, sl, v.raw);
+  }
   R rho, j[3];
   site_prepare(v, d, src, sl, rho, j, true);
   const AlphaOut<R> ao = choose_alpha<MODE, kPhaseRare>(v, d);

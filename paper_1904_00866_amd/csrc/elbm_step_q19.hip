@@ -46,7 +46,7 @@ struct SiteQ19 {
   static constexpr int Q = 19;
   static constexpr int kDim = 3;
   static constexpr bool kZFactor = false;
-  T raw[Q];
+  typename Kept<S>::type raw[Q];  // the loaded populations as kept (Kept<S>)
   R rho, irho, rho_ref;
   R u[3];
   // f^eq_i = F0[dx][dy] (c_z = 0) or F1[dx][dy] e2[dz] (c_z != 0); the
@@ -257,7 +257,7 @@ __device__ __forceinline__ SiteOut update_q19(const SimDesc& d, const typename S
   const uint32_t sl = live ? s : 0u;
   SiteQ19<S, R> v;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v.raw[i] = raw[i];
+  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
   R rho, j[3];
   prepare_q19(v, d, src, sl, rho, j, MODE != kBGK);
   const R beta = (R)d.beta;
@@ -325,7 +325,14 @@ __device__ __forceinline__ uint32_t update_rare_q19(const SimDesc& d,
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;
   SiteQ19<S, R> v;
-  load_q19(d, src, sl, v.raw);
+  if constexpr (Codec<S, R>::kF16) {
+    T raw[Q];
+    load_q19(d, src, sl, raw);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
+  } else {
+    load_q19(d, src, sl, v.raw);
+  }
   R rho, j[3];
   prepare_q19(v, d, src, sl, rho, j, true);
   const AlphaOut<R> ao = choose_alpha<MODE, kPhaseRare>(v, d);
