@@ -189,15 +189,18 @@ def w4(n=256, T=2000):
     W = torch.tensor([wa[a] * wa[b] * wa[c] for a, b, c in L], dtype=torch.float64,
                      device="cuda")
     ulp = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "f32dev": 2.0 ** -24, "f16dev": 2.0 ** -11}
-    cases = [("f64", True), ("f32", True), ("f32dev", True), ("f16dev", True),
-             ("f32", False), ("f16dev", False)]
+    # (storage, site arithmetic): FP64 throughout; mixed (FP32 moments,
+    # equilibrium and collision, FP64 alpha evaluation); FP32 throughout
+    cases = [("f64", "fp64"), ("f32", "fp64"), ("f32dev", "fp64"), ("f16dev", "fp64"),
+             ("f32", "mixed"), ("f32dev", "mixed"), ("f16dev", "mixed"),
+             ("f32", "fp32"), ("f16dev", "fp32")]
     out = {"experiment": "w4", "workload": f"D3Q27 Taylor-Green {n}^3, u0 = 0.05, Re = 1600 "
            f"(beta = {beta:.6f}), {T} steps, closed-form alpha", "cases": {}}
     ref = None
     sites = torch.arange(N, dtype=torch.int64, device="cuda")
-    for storage, fp64 in cases:
-        name = f"{storage}/{'fp64' if fp64 else 'fp32'}-arith"
-        with elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, storage=storage, fp64=fp64,
+    for storage, arith in cases:
+        name = f"{storage}/{arith}-arith"
+        with elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, storage=storage, fp64=arith,
                              beta=beta, diag=elbm.DIAG_COUNTS | elbm.DIAG_SUMS) as sim:
             Hsum, neg = [], 0
             for t in range(0, T, 100):

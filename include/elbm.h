@@ -104,6 +104,22 @@ enum {
   ELBM_STORE_F16_DEV = 3
 };
 
+/* Site arithmetic (elbm_config.alpha_fp64).  The paper computes in FP64
+ * throughout.
+ *   FP64:  moments, equilibrium, x_i = f_i / f^eq_i - 1, the entropy
+ *          differences, alpha and the collision in FP64; one rounding into
+ *          the storage format.  Every alpha mode, every storage format.
+ *   FP32:  all of it in FP32 on f_i (closed-form alpha; FP32 and deviation
+ *          storage).
+ *   MIXED: FP32 arithmetic on the deviations s_i = f_i / W_i - rho_ref:
+ *          moments, the equilibrium as s^eq_i = f^eq_i / W_i - rho_ref
+ *          (formed without cancellation), x_i = (s_i - s^eq_i) /
+ *          (rho_ref + s^eq_i) and the collision s~_i = s_i + alpha beta
+ *          (s^eq_i - s_i); the entropy differences of Eqs. (7)-(9) and alpha
+ *          in FP64.  Closed-form alpha; FP32 and deviation storage; D1Q3,
+ *          D2Q9 and D3Q27 with the Boltzmann entropy. */
+enum { ELBM_ARITH_FP32 = 0, ELBM_ARITH_FP64 = 1, ELBM_ARITH_MIXED = 2 };
+
 /* Entropy function.  The paper states the scheme for the Boltzmann entropy
  * of Eq. (3) and remarks that the closed form (Eq. (9)) needs only a convex
  * entropy; the library also runs it with Burg's entropy
@@ -130,9 +146,10 @@ typedef struct {
   double beta;           /* Eq. (2), 0 < beta < 1                         */
   int32_t alpha_mode;    /* ELBM_ALPHA_*                                  */
   int32_t storage;       /* ELBM_STORE_*                                  */
-  int32_t alpha_fp64;    /* 1: site arithmetic in FP64 (required for
-                            STORE_F64); 0: FP32 arithmetic (closed mode,
-                            FP32/FP16 storage only)                       */
+  int32_t alpha_fp64;    /* ELBM_ARITH_*: FP64 (the default; required
+                            for STORE_F64 and the root and secant modes),
+                            FP32 or MIXED (closed mode, FP32 and deviation
+                            storage)                                      */
   int32_t secant_iters;  /* iterations of ELBM_ALPHA_SECANT (>= 1)        */
   double rho_ref;        /* reference density of *_DEV storage (> 0)      */
   double root_tol;       /* bisection window; the paper uses 1e-13        */

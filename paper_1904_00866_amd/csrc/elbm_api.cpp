@@ -17,6 +17,13 @@
 
 using namespace elbm;
 
+static_assert(kStoreF64 == ELBM_STORE_F64 && kStoreF32 == ELBM_STORE_F32 &&
+                  kStoreF32Dev == ELBM_STORE_F32_DEV && kStoreF16Dev == ELBM_STORE_F16_DEV,
+              "storage codes");
+static_assert(kArithF32 == ELBM_ARITH_FP32 && kArithF64 == ELBM_ARITH_FP64 &&
+                  kArithMixed == ELBM_ARITH_MIXED,
+              "arithmetic codes");
+
 namespace {
 
 thread_local std::string g_err;
@@ -77,11 +84,13 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
     return fail(ELBM_EINVAL, "unknown alpha mode %d", c->alpha_mode);
   const int es = elem_size(c->storage);
   if (!es) return fail(ELBM_EINVAL, "unknown storage %d", c->storage);
-  if (c->alpha_fp64 != 0 && c->alpha_fp64 != 1) return fail(ELBM_EINVAL, "alpha_fp64 must be 0 or 1");
-  if (!c->alpha_fp64 && c->storage == ELBM_STORE_F64)
+  if (c->alpha_fp64 != ELBM_ARITH_FP32 && c->alpha_fp64 != ELBM_ARITH_FP64 &&
+      c->alpha_fp64 != ELBM_ARITH_MIXED)
+    return fail(ELBM_EINVAL, "alpha_fp64 must be ELBM_ARITH_FP32, _FP64 or _MIXED");
+  if (c->alpha_fp64 != ELBM_ARITH_FP64 && c->storage == ELBM_STORE_F64)
     return fail(ELBM_EUNSUPPORTED, "FP64 storage needs FP64 arithmetic");
-  if (!c->alpha_fp64 && c->alpha_mode != ELBM_ALPHA_CLOSED)
-    return fail(ELBM_EUNSUPPORTED, "FP32 arithmetic is built for the closed-form alpha only");
+  if (c->alpha_fp64 != ELBM_ARITH_FP64 && c->alpha_mode != ELBM_ALPHA_CLOSED)
+    return fail(ELBM_EUNSUPPORTED, "FP32 and mixed arithmetic are built for the closed-form alpha only");
   if ((c->storage == ELBM_STORE_F32_DEV || c->storage == ELBM_STORE_F16_DEV) &&
       !(c->rho_ref > 0.0 && std::isfinite(c->rho_ref)))
     return fail(ELBM_EINVAL, "rho_ref must be > 0 for deviation storage");

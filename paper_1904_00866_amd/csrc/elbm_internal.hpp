@@ -26,6 +26,8 @@ constexpr int kDiagAlpha = 1, kDiagCounts = 2, kDiagSums = 4;
 
 // Storage codes (same values as ELBM_STORE_*).
 constexpr int kStoreF64 = 0, kStoreF32 = 1, kStoreF32Dev = 2, kStoreF16Dev = 3;
+// Site arithmetic codes (same values as ELBM_ARITH_*).
+constexpr int kArithF32 = 0, kArithF64 = 1, kArithMixed = 2;
 
 // Alpha modes (same values as ELBM_ALPHA_*).
 constexpr int kClosed = 0, kNewton = 1, kBisect = 2, kBGK = 3, kSecant = 4;

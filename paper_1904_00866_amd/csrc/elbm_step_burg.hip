@@ -383,7 +383,7 @@ StepLauncher burg_for(int storage, int mode) {
 }  // namespace
 
 StepLauncher step_launcher_burg(int lattice, int storage, int mode, int fp64) {
-  if (!fp64) return nullptr;
+  if (fp64 != kArithF64) return nullptr;
   switch (lattice) {
     case 1: return burg_for<Lattice<1>>(storage, mode);
     case 2: return burg_for<Lattice<2>>(storage, mode);

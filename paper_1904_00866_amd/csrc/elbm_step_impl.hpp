@@ -350,6 +350,126 @@ struct Site {
   }
 };
 
+// --------------------------------------------------- deviation arithmetic --
+// The site of the mixed arithmetic policy.  Its FP32 arithmetic acts on the
+// deviations s_i = f_i / W_i - rho_ref, which are O(|u| + |x|), so that each
+// rounding is relative to a deviation rather than to f_i ~ W_i rho (FP32
+// arithmetic on f_i itself drifts: the equilibrium's rounding, a smooth
+// function of u, adds up over the steps).  With sum_i W_i = 1 and
+// sum_i W_i c_i = 0:
+//   rho = rho_ref + dr, dr = sum_i W_i s_i;  rho u = sum_i W_i c_i s_i.
+// The equilibrium's per-axis factors A_a z_a^c are written 1 + dl_a(c), with
+// the deviations dl formed without cancellation from q = s_a - 1 =
+// 3u^2 / (1 + s_a), s_a = sqrt(1 + 3u^2):
+//   dl(0) = A - 1 = -q,   dl(+1) = A z - 1 = (1 - q)(1 + dz) - 1,
+//   dl(-1) = A / z - 1 = (1 - q)(1 + dzi) - 1,
+//   dz = z - 1 = (3u + q) / (1 - u),   dzi = 1/z - 1 = -(3u + q) / (2u + s_a);
+// then f^eq_i / W_i = rho (1 + Dl_i), Dl_i = prod_a (1 + dl_a) - 1 expanded
+// pairwise, and s^eq_i = dr + rho Dl_i.  The entropy differences and alpha
+// are evaluated in FP64 from
+//   x_i = f_i / f^eq_i - 1 = (s_i - s^eq_i) / (rho_ref + s^eq_i)
+// and f^eq_i = W_i (rho_ref + s^eq_i), and the collision (Eq. (1)) is
+//   s~_i = s_i + alpha beta (s^eq_i - s_i).
+template <int D, class S>
+struct SiteDev {
+  using L = Lattice<D>;
+  using T = typename S::T;
+  using Real = double;  // arithmetic of the alpha evaluation
+  static constexpr int Q = L::Q;
+  static constexpr int kDim = D;
+  static constexpr bool kZFactor = false;  // f^eq_i comes from s^eq_i
+  typename Kept<S>::type raw[Q];
+  float r, dr, rho32;  // rho_ref, rho - rho_ref, rho
+  double rho, u[3];    // rho and u widened (alpha's guard, diagnostics)
+  float dxy[3][3];     // (1 + dl_x(dx)) (1 + dl_y(dy)) - 1
+  float dlz[3];        // dl_z(dz)
+  const T* src;
+  uint32_t site;
+  const SimDesc* desc;
+  Where w;  // filled by locate() before a rare-path loop
+
+  // s_i from the kept value (FP32 storage holds f_i: one rounding)
+  __device__ __forceinline__ float s(int i) const {
+    if constexpr (S::dev) return raw[i];
+    else return fmaf(raw[i], float(L::invW(i)), -r);
+  }
+  struct Pass {
+    float dlz[3];
+  };
+  __device__ __forceinline__ Pass pass() const {
+    Pass p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p.dlz[k] = dlz[k];
+    return p;
+  }
+  // copies hidden from the optimiser, so that the s^eq_i of different
+  // passes are not kept live between them
+  __device__ __forceinline__ Pass pass_opaque() const {
+    Pass p;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p.dlz[k] = opaque(dlz[k]);
+    return p;
+  }
+  __device__ __forceinline__ float seq(int i, const Pass& p) const {
+    const float a = dxy[L::dg(i, 0)][L::dg(i, 1)];
+    const float b = p.dlz[L::dg(i, 2)];
+    return fmaf(rho32, D > 2 ? fmaf(a, b, a + b) : a, dr);
+  }
+  __device__ __forceinline__ double fe(int i, const Pass& p) const {
+    return double(float(L::W(i)) * (r + seq(i, p)));
+  }
+  __device__ __forceinline__ double x(int i, const Pass& p) const {
+    const float q = seq(i, p);
+    return double((s(i) - q) * __builtin_amdgcn_rcpf(r + q));
+  }
+  // the stored value of s~_i
+  __device__ __forceinline__ T enc(int i, float sn) const {
+    if constexpr (S::dev) return T(sn);
+    else return T(fmaf(float(L::W(i)), sn, float(L::W(i)) * r));
+  }
+
+  // H(f^eq) / rho, as for the FP64 site
+  __device__ __forceinline__ double heq_per_rho() const {
+    double h = log(rho);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double ua = u[a];
+      const double sa = sqrt(1.0 + 3.0 * ua * ua);
+      h += log(2.0 - sa) + ua * log((2.0 * ua + sa) / (1.0 - ua));
+    }
+    return h;
+  }
+
+  // -- loop accessors (run-time, wavefront-uniform i) -----------------------
+  // The population is re-read from the source buffer (see Site::xfe).
+  // W_i = num / den with num = 4^(number of zero components of c_i); both
+  // quotients round as float(L::W(i)) and float(L::invW(i)) do (den / num is
+  // exact)
+  __device__ __forceinline__ static float weight_num(int i) {
+    const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
+    const int nz0 = (dx == 0) + (D > 1 && dy == 0) + (D > 2 && dz == 0);
+    return nz0 == 0 ? 1.0f : nz0 == 1 ? 4.0f : nz0 == 2 ? 16.0f : 64.0f;
+  }
+  __device__ __forceinline__ static float weight_of(int i) { return weight_num(i) / float(L::den()); }
+  __device__ __forceinline__ static float invweight_of(int i) { return float(L::den()) / weight_num(i); }
+  __device__ __forceinline__ void sq(int i, float& si, float& seqi) const {
+    const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
+    const uint32_t sp = sel3(w.zs, dz) + sel3(w.ys, dy) + sel3(w.xs, dx);
+    const T gv = *(const gptr<T>)((gaddr)(uintptr_t)src + pidx<Q>(sp, i) * sizeof(T));
+    if constexpr (S::dev) si = float(gv);
+    else si = fmaf(float(gv), invweight_of(i), -r);
+    // the selections multiply by 0 and 1 and add zeros: exact
+    const float a = sel9(dxy, dx, dy), b = sel3(dlz, dz);
+    seqi = fmaf(rho32, D > 2 ? fmaf(a, b, a + b) : a, dr);
+  }
+  __device__ __forceinline__ void xfe(int i, double& xi, double& fi, double* = nullptr) const {
+    float si, seqi;
+    sq(i, si, seqi);
+    xi = double((si - seqi) * __builtin_amdgcn_rcpf(r + seqi));
+    fi = double(weight_of(i) * (r + seqi));
+  }
+};
+
 // S(a) = sum_i f^eq_i phi((1 - a) x_i); G(a) = H(f*(a)) - H(f) = S(a) - D.
 template <class V, class R>
 __device__ __forceinline__ R S_log(const V& v, R a) {
@@ -821,8 +941,8 @@ __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32
 // rho and rho u of a site, summed per x-row of directions first: for each
 // (c_y, c_z) the three directions c_x = 0, +1, -1 give a row sum and an
 // x-momentum term.
-template <int D, class S, class R>
-__device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (&j)[3]) {
+template <int D, class R, class G>
+__device__ __forceinline__ void moments_of(const G& g, R& rho, R (&j)[3]) {
   constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
   R rs[3][3], rx[3][3];
 #pragma unroll
@@ -830,7 +950,7 @@ __device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (
 #pragma unroll
     for (int dy = 0; dy < NY; ++dy) {
       const int i0 = 9 * dz + 3 * dy;
-      const R g0 = v.g(i0), gp = v.g(i0 + 1), gm = v.g(i0 + 2);
+      const R g0 = g(i0), gp = g(i0 + 1), gm = g(i0 + 2);
       rs[dy][dz] = g0 + (gp + gm);
       rx[dy][dz] = gp - gm;
     }
@@ -859,6 +979,10 @@ __device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (
   }
   if constexpr (D > 2) j[2] = cz[1] - cz[2];
 }
+template <int D, class S, class R>
+__device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (&j)[3]) {
+  moments_of<D>([&](int i) { return v.g(i); }, rho, j);
+}
 
 // Loads (or takes) the site's populations, forms rho, u and, for the
 // entropic modes, the equilibrium factors.
@@ -881,6 +1005,70 @@ __device__ __forceinline__ void site_prepare(Site<D, S, R>& v, const SimDesc& d,
     eq.build(v.u);
     v.fold(eq);
   }
+}
+
+// Arithmetic policies: R = double (all FP64) or float (all FP32) is the
+// site arithmetic itself; Mixed runs FP32 arithmetic on the deviations
+// (SiteDev) and evaluates the entropy differences and alpha in FP64.
+// SiteReal names the type of the alpha evaluation.
+struct Mixed {};
+template <class P>
+struct SiteReal {
+  using type = P;
+};
+template <>
+struct SiteReal<Mixed> {
+  using type = double;
+};
+template <class P>
+constexpr bool kIsMixed = std::is_same<P, Mixed>::value;
+
+// The mixed policy's preparation (SiteDev): moments of the deviations and
+// the per-axis deviations dl of the equilibrium factors.
+template <int D, class S>
+__device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc& d,
+                                                 const typename S::T* src, uint32_t sl,
+                                                 double (&j)[3]) {
+  using L = Lattice<D>;
+  v.src = src;
+  v.site = sl;
+  v.desc = &d;
+  v.r = float(d.rho_ref);
+  float dr, j32[3];
+  moments_of<D>([&](int i) { return float(L::W(i)) * v.s(i); }, dr, j32);
+  const float rho32 = v.r + dr;
+  const float irho = rcp_n<float>(rho32);
+  float dl[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) {
+      const float ua = j32[a] * irho, t = 3.0f * ua * ua;
+      const float sa = sqrt_n<float>(1.0f + t);
+      const float q = t * __builtin_amdgcn_rcpf(1.0f + sa);
+      const float pz = fmaf(3.0f, ua, q);
+      const float dz = pz * __builtin_amdgcn_rcpf(1.0f - ua);
+      const float dzi = -pz * __builtin_amdgcn_rcpf(fmaf(2.0f, ua, sa));
+      dl[a][0] = -q;
+      dl[a][1] = fmaf(-q, dz, dz - q);
+      dl[a][2] = fmaf(-q, dzi, dzi - q);
+      v.u[a] = ua;
+    } else {
+      dl[a][0] = dl[a][1] = dl[a][2] = 0.0f;
+      v.u[a] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      v.dxy[a][b] = D > 1 ? fmaf(dl[0][a], dl[1][b], dl[0][a] + dl[1][b]) : dl[0][a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v.dlz[k] = dl[2][k];
+  v.dr = dr;
+  v.rho32 = rho32;
+  v.rho = rho32;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) j[a] = j32[a];
 }
 
 // Count predicates of one site as bits kCnt*: they are turned into
@@ -935,7 +1123,7 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
 //
 // PHASE (closed form): kPhaseCommon leaves the lanes that need the rare
 // tier untouched and returns true for them; site_update_rare completes them.
-template <int D, class S, int MODE, class R, bool SUMS, int PHASE = kPhaseAll>
+template <int D, class S, int MODE, class AP, bool SUMS, int PHASE = kPhaseAll>
 __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename S::T* __restrict__ src,
                                             typename S::T* __restrict__ dst, uint32_t s,
                                             bool live, const typename S::T (&raw)[Lattice<D>::Q],
@@ -943,9 +1131,34 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
+  using R = typename SiteReal<AP>::type;  // arithmetic of the site type
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;  // the site whose values were loaded
 
+  if constexpr (kIsMixed<AP>) {
+    // the mixed policy (closed form): FP32 on the deviations, FP64 alpha
+    SiteDev<D, S> v;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+    double j[3];
+    site_prepare_dev(v, d, src, sl, j);
+    const AlphaOut<double> ao = choose_alpha<MODE, PHASE>(v, d);
+    if (PHASE == kPhaseCommon && ao.deferred) return SiteOut{true, 0u};
+    const float ab = float(ao.alpha * d.beta);
+    const auto P = v.pass_opaque();
+    float tmin = INFINITY;  // min of f~_i / W_i: its sign is that of f~_i
+    const uint32_t lo = (s & 63u) * es;
+    const gaddr blk = block_base<Q>(dst, s);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float si = v.s(i);
+      const float sn = fmaf(ab, v.seq(i, P) - si, si);
+      if constexpr (PHASE != kPhaseCommon) tmin = fminf(tmin, v.r + sn);
+      st_nt<T>(blk + i * kLane * es, kLane * es, lo, v.enc(i, sn));
+      sched_group(i);
+    }
+    return SiteOut{false, record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag)};
+  }
   Site<D, S, R> v;
 #pragma unroll
   for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
@@ -1018,7 +1231,7 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
 // equilibrium recomputed by the same arithmetic, alpha taken from the rare
 // tier, and the collision run as a rolled loop that re-reads each
 // population, so no per-direction array stays live across the logarithms.
-template <int D, class S, int MODE, class R, bool SUMS>
+template <int D, class S, int MODE, class AP, bool SUMS>
 __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
                                                  const typename S::T* __restrict__ src,
                                                  typename S::T* __restrict__ dst, uint32_t s,
@@ -1026,8 +1239,43 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
+  using R = typename SiteReal<AP>::type;
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;
+  if constexpr (kIsMixed<AP>) {
+    SiteDev<D, S> v;
+    if constexpr (Codec<S, double>::kF16) {
+      T raw[Q];
+      load_site<D>(d, src, sl, raw);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+    } else {
+      load_site<D>(d, src, sl, v.raw);
+    }
+    double j[3];
+    site_prepare_dev(v, d, src, sl, j);
+    const AlphaOut<double> ao = choose_alpha<MODE, kPhaseRare>(v, d);
+    const float ab = float(ao.alpha * d.beta);
+    float tmin = INFINITY;
+    const uint32_t lo = (s & 63u) * es;
+    const gaddr blk = block_base<Q>(dst, s);
+#pragma unroll 1
+    for (int i = 0; i < Q; ++i) {
+      float si, seqi;
+      v.sq(i, si, seqi);
+      const float sn = fmaf(ab, seqi - si, si);
+      tmin = fminf(tmin, v.r + sn);
+      T out;
+      if constexpr (S::dev) {
+        out = T(sn);
+      } else {
+        const float W = SiteDev<D, S>::weight_of(i);
+        out = T(fmaf(W, sn, W * v.r));
+      }
+      st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, out);
+    }
+    return record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag);
+  }
   Site<D, S, R> v;
   if constexpr (Codec<S, R>::kF16) {
     T raw[Q];
@@ -1040,10 +1288,10 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
   R rho, j[3];
   site_prepare(v, d, src, sl, rho, j, true);
   const AlphaOut<R> ao = choose_alpha<MODE, kPhaseRare>(v, d);
-  const R ab = ao.alpha * (R)d.beta;
-  R ftmin = R(INFINITY);
   const uint32_t lo = (s & 63u) * es;
   const gaddr blk = block_base<Q>(dst, s);
+  const R ab = ao.alpha * (R)d.beta;
+  R ftmin = R(INFINITY);
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
     R xi, fi, gi;
@@ -1195,7 +1443,7 @@ StepLauncher step_launcher_for(int storage, int mode, int fp64) {
     case kSecant: return &launch_step<D, S, kSecant, R>;      \
     default: return nullptr;                                  \
   }
-  if (fp64) {
+  if (fp64 == kArithF64) {
     switch (storage) {
       case kStoreF64: ELBM_MODES(StoreF64, double)
       case kStoreF32: ELBM_MODES(StoreF32, double)
@@ -1206,6 +1454,15 @@ StepLauncher step_launcher_for(int storage, int mode, int fp64) {
   }
 #undef ELBM_MODES
   if (mode != kClosed) return nullptr;
+  if (fp64 == kArithMixed) {
+    switch (storage) {
+      case kStoreF32: return &launch_step<D, StoreF32, kClosed, Mixed>;
+      case kStoreF32Dev: return &launch_step<D, StoreF32Dev, kClosed, Mixed>;
+      case kStoreF16Dev: return &launch_step<D, StoreF16Dev, kClosed, Mixed>;
+      default: return nullptr;
+    }
+  }
+  if (fp64 != kArithF32) return nullptr;
   switch (storage) {
     case kStoreF32: return &launch_step<D, StoreF32, kClosed, float>;
     case kStoreF32Dev: return &launch_step<D, StoreF32Dev, kClosed, float>;

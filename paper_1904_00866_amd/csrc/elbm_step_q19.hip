@@ -460,7 +460,7 @@ StepLauncher step_launcher_q19(int storage, int mode, int fp64) {
     case kSecant: return &launch_q19<S, kSecant, R>;     \
     default: return nullptr;                             \
   }
-  if (fp64) {
+  if (fp64 == kArithF64) {
     switch (storage) {
       case kStoreF64: ELBM_MODES(StoreF64, double)
       case kStoreF32: ELBM_MODES(StoreF32, double)
@@ -470,7 +470,7 @@ StepLauncher step_launcher_q19(int storage, int mode, int fp64) {
     }
   }
 #undef ELBM_MODES
-  if (mode != kClosed) return nullptr;
+  if (mode != kClosed || fp64 != kArithF32) return nullptr;
   switch (storage) {
     case kStoreF32: return &launch_q19<StoreF32, kClosed, float>;
     case kStoreF32Dev: return &launch_q19<StoreF32Dev, kClosed, float>;

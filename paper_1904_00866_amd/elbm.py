@@ -28,6 +28,7 @@ MODES = {"closed": 0, "newton": 1, "bisect": 2, "bgk": 3, "secant": 4}
 STORAGES = {"f64": 0, "f32": 1, "f32dev": 2, "f16dev": 3}
 DIAG_ALPHA, DIAG_COUNTS, DIAG_SUMS = 1, 2, 4
 ENTROPIES = {"boltzmann": 0, "burg": 1}
+ARITH = {"fp32": 0, "fp64": 1, "mixed": 2}
 STATUS = {0: "ELBM_OK", -1: "ELBM_EINVAL", -2: "ELBM_EDEVICE", -3: "ELBM_ENOMEM",
           -4: "ELBM_ESTATE", -5: "ELBM_EUNSUPPORTED"}
 EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_populations",
@@ -153,7 +154,8 @@ def make_config(lattice, nx, ny=1, nz=1, *, beta=0.95, mode="closed", storage="f
     cfg.beta = float(beta)
     cfg.alpha_mode = MODES[mode] if isinstance(mode, str) else int(mode)
     cfg.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
-    cfg.alpha_fp64 = 1 if fp64 else 0
+    # fp64: True / False, or an ARITH name ("fp64", "fp32", "mixed")
+    cfg.alpha_fp64 = ARITH[fp64] if isinstance(fp64, str) else (1 if fp64 else 0)
     cfg.secant_iters = int(secant_iters)
     cfg.rho_ref = float(rho_ref)
     cfg.root_tol = float(root_tol)

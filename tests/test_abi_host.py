@@ -113,6 +113,28 @@ def test_burg_entropy_configs():
         elbm.state_bytes(c)
 
 
+def test_mixed_arithmetic_configs():
+    """ELBM_ARITH_MIXED (FP32 site arithmetic, FP64 alpha evaluation) is
+    built for the closed form on the tensor-product lattices with FP32 and
+    deviation storage and the Boltzmann entropy; other combinations report
+    that no kernel exists, and unknown codes are rejected."""
+    for lat, shape in (("d1q3", (64, 1, 1)), ("d2q9", (16, 16, 1)), ("d3q27", (8, 8, 8))):
+        for storage in ("f32", "f32dev", "f16dev"):
+            cfg = elbm.make_config(lat, *shape, storage=storage, fp64="mixed")
+            assert cfg.alpha_fp64 == 2
+            assert elbm.state_bytes(cfg) > 0
+    for kw in (dict(lattice="d3q19"), dict(entropy="burg")):
+        args = dict(lattice="d2q9", fp64="mixed")
+        args.update(kw)
+        lat = args.pop("lattice")
+        with pytest.raises(elbm.ElbmError, match="no kernel"):
+            elbm.state_bytes(elbm.make_config(lat, 8, 8, 8 if lat == "d3q19" else 1, **args))
+    c = elbm.make_config("d2q9", 16, 16)
+    c.alpha_fp64 = 3
+    with pytest.raises(elbm.ElbmError, match="alpha_fp64"):
+        elbm.state_bytes(c)
+
+
 def test_large_boxes_fit_the_layout():
     """A 1024^3 FP32 D3Q27 state (232 GB with both buffers) is a valid
     configuration: the blocked layout has no per-buffer size limit."""
@@ -124,8 +146,10 @@ def test_large_boxes_fit_the_layout():
 @pytest.mark.parametrize("kw,msg", [
     (dict(beta=1.0), "beta"),
     (dict(beta=0.0), "beta"),
-    (dict(mode="newton", fp64=False), "FP32 arithmetic"),
+    (dict(mode="newton", fp64=False), "closed-form alpha only"),
+    (dict(mode="bgk", fp64="mixed"), "closed-form alpha only"),
     (dict(storage="f64", fp64=False), "FP64 storage"),
+    (dict(storage="f64", fp64="mixed"), "FP64 storage"),
     (dict(diag=elbm.DIAG_SUMS), "SUMS"),
     (dict(diag=64), "diagnostics"),
     (dict(storage="f16dev", rho_ref=0.0), "rho_ref"),

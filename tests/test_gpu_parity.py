@@ -233,6 +233,64 @@ def test_fp32_arithmetic_ablation(gpu, orc):
     sim.close()
 
 
+@pytest.mark.parametrize("D,rows", [(1, False), (2, False), (2, True), (3, False), (3, True)])
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
+def test_mixed_arithmetic_one_step(gpu, orc, D, rows, storage):
+    """Mixed arithmetic (FP32 arithmetic on the deviations s_i = f_i/W_i -
+    rho_ref, entropy differences and alpha in FP64): one step from the
+    decoded stored state against the FP64 oracle.  Populations: 2e-6
+    relative (the FP32 arithmetic) plus one rounding into the storage format;
+    alpha: 1e-5 (x_i carries the FP32 equilibrium's rounding)."""
+    shape = (ROW_SHAPES if rows else SHAPES)[D]
+    N = int(np.prod(shape))
+    f0 = _random_state(D, N, seed=900 + 10 * D + len(storage) + rows, eps=0.02, tilt=0.05)
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.97, fp64="mixed",
+               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS)
+    fq = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    fo, ao, d = orc.step(_ocfg(orc, D, shape, beta=0.97), fq, want_alpha=True, want_diag=True)
+    W = H.textbook_weights(D)[:, None]
+    tol = 2e-6 * np.abs(fo)
+    if storage == "f16dev":
+        tol = tol + W * 2.0 ** -11 * np.abs(fo / W - 1.0) * 1.01
+    assert np.all(np.abs(fg - fo) <= tol)
+    assert np.max(np.abs(ag - ao)) <= 1e-5
+    st = sim.stats()
+    assert 0 < st["n_alpha_lt2"] < N
+    assert st["n_negative"] == 0 and st["n_nonfinite"] == 0
+    sim.close()
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_mixed_arithmetic_far_from_equilibrium(gpu, orc, D):
+    """The rare tier under mixed arithmetic (alpha_* < 2 on many sites, the
+    log1p forms, the rolled FP32 collision): one step, FP32 storage, error
+    4e-6 of the larger of the old and new population (far from equilibrium
+    the FP32 term alpha beta (f^eq_i - f_i) can exceed both populations, and
+    f^eq_i carries the FP32 equilibrium's rounding)."""
+    shape = SHAPES[D]
+    N = int(np.prod(shape))
+    f0 = Wk.random_populations(H.textbook_weights(D), N, 0.7, 940 + D, tilt=0.2,
+                               log_uniform_eps=False)
+    sim = _sim(gpu, D, shape, f0, storage="f32", beta=0.9, fp64="mixed",
+               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS)
+    fq = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    fo, ao, d = orc.step(_ocfg(orc, D, shape, beta=0.9), fq, want_alpha=True, want_diag=True)
+    assert d["n_alphastar_lt2"] > N // 20
+    r = np.abs(fg - fo) / np.maximum(np.abs(fo), np.abs(fq))
+    k = np.unravel_index(np.argmax(r), r.shape)
+    s = k[1]
+    assert r[k] <= 4e-6, (r[k], k, ag[s], ao[s], fq[:, s], fo[:, s], fg[:, s])
+    assert np.max(np.abs(ag - ao)) <= 1e-5
+    assert sim.stats()["n_alphastar_lt2"] == d["n_alphastar_lt2"]
+    sim.close()
+
+
 def test_d3q27_multistep_fp64_ragged(gpu, orc):
     shape = (24, 20, 18)
     N = int(np.prod(shape))
