@@ -358,13 +358,13 @@ struct Site {
 // function of u, adds up over the steps).  With sum_i W_i = 1 and
 // sum_i W_i c_i = 0:
 //   rho = rho_ref + dr, dr = sum_i W_i s_i;  rho u = sum_i W_i c_i s_i.
-// The equilibrium's per-axis factors A_a z_a^c are written 1 + dl_a(c), with
-// the deviations dl formed without cancellation from q = s_a - 1 =
-// 3u^2 / (1 + s_a), s_a = sqrt(1 + 3u^2):
-//   dl(0) = A - 1 = -q,   dl(+1) = A z - 1 = (1 - q)(1 + dz) - 1,
-//   dl(-1) = A / z - 1 = (1 - q)(1 + dzi) - 1,
-//   dz = z - 1 = (3u + q) / (1 - u),   dzi = 1/z - 1 = -(3u + q) / (2u + s_a);
-// then f^eq_i / W_i = rho (1 + Dl_i), Dl_i = prod_a (1 + dl_a) - 1 expanded
+// The equilibrium's per-axis factors A_a z_a^c are written 1 + dl_a(c).  With
+// s_a = sqrt(1 + 3u^2) and q = s_a - 1 = 3u^2 / (1 + s_a) (no cancellation),
+// the factors are A = 1 - q and A z^(+-1) = 2 s_a - 1 +- 3u (expand
+// (1 - q)(1 + 2u + q) - (1 - u) and use q^2 + 2q = 3u^2), so
+//   dl(0) = -q,   dl(+-1) = 2q +- 3u,
+// one rounding each; sum_c w(c) dl(c) = 0 and sum_c w(c) c dl(c) = u then
+// hold up to those roundings; then f^eq_i / W_i = rho (1 + Dl_i), Dl_i = prod_a (1 + dl_a) - 1 expanded
 // pairwise, and s^eq_i = dr + rho Dl_i.  The entropy differences and alpha
 // are evaluated in FP64 from
 //   x_i = f_i / f^eq_i - 1 = (s_i - s^eq_i) / (rho_ref + s^eq_i)
@@ -422,10 +422,18 @@ struct SiteDev {
     const float q = seq(i, p);
     return double((s(i) - q) * __builtin_amdgcn_rcpf(r + q));
   }
-  // the stored value of s~_i
+  // the stored value of s~_i.  FP32 storage holds f~_i = W_i (rho_ref + s~_i),
+  // rounded once from W_i = wh + wl (wl: the residual of W_i's FP32
+  // rounding): with the FP32 weight alone every step would scale f_i by
+  // float(W_i) / W_i, a bias that adds up (the read divides by 1 / W_i, which
+  // is exact).
+  __host__ __device__ static constexpr float w_lo(double W) { return float(W - double(float(W))); }
+  __device__ __forceinline__ static T enc_f(float wh, float wl, float rr, float sn) {
+    return T(fmaf(wh, rr, fmaf(wh, sn, wl * (rr + sn))));
+  }
   __device__ __forceinline__ T enc(int i, float sn) const {
     if constexpr (S::dev) return T(sn);
-    else return T(fmaf(float(L::W(i)), sn, float(L::W(i)) * r));
+    else return enc_f(float(L::W(i)), w_lo(L::W(i)), r, sn);
   }
 
   // H(f^eq) / rho, as for the FP64 site
@@ -451,6 +459,12 @@ struct SiteDev {
     return nz0 == 0 ? 1.0f : nz0 == 1 ? 4.0f : nz0 == 2 ? 16.0f : 64.0f;
   }
   __device__ __forceinline__ static float weight_of(int i) { return weight_num(i) / float(L::den()); }
+  // w_lo of the weight weight_of(i) rounds (the four weights of the lattice)
+  __device__ __forceinline__ static float weight_lo(int i) {
+    const float n = weight_num(i);
+    return n == 1.0f ? w_lo(1.0 / L::den()) : n == 4.0f ? w_lo(4.0 / L::den())
+         : n == 16.0f ? w_lo(16.0 / L::den()) : w_lo(64.0 / L::den());
+  }
   __device__ __forceinline__ static float invweight_of(int i) { return float(L::den()) / weight_num(i); }
   __device__ __forceinline__ void sq(int i, float& si, float& seqi) const {
     const int dx = i % 3, dy = D > 1 ? (i / 3) % 3 : 0, dz = D > 2 ? i / 9 : 0;
@@ -1034,8 +1048,17 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
   v.site = sl;
   v.desc = &d;
   v.r = float(d.rho_ref);
+  // W_i s_i with W_i = wh + wl, rounded once: with the FP32 weight alone the
+  // moments are biased by float(W_i) / W_i, and the collision hands the bias
+  // on to the state at every step (rho u grows by about alpha beta 2e-8 per
+  // step)
   float dr, j32[3];
-  moments_of<D>([&](int i) { return float(L::W(i)) * v.s(i); }, dr, j32);
+  moments_of<D>(
+      [&](int i) {
+        const float si = v.s(i);
+        return fmaf(float(L::W(i)), si, SiteDev<D, S>::w_lo(L::W(i)) * si);
+      },
+      dr, j32);
   const float rho32 = v.r + dr;
   const float irho = rcp_n<float>(rho32);
   float dl[3][3];
@@ -1043,14 +1066,10 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
       const float ua = j32[a] * irho, t = 3.0f * ua * ua;
-      const float sa = sqrt_n<float>(1.0f + t);
-      const float q = t * __builtin_amdgcn_rcpf(1.0f + sa);
-      const float pz = fmaf(3.0f, ua, q);
-      const float dz = pz * __builtin_amdgcn_rcpf(1.0f - ua);
-      const float dzi = -pz * __builtin_amdgcn_rcpf(fmaf(2.0f, ua, sa));
+      const float q = t * __builtin_amdgcn_rcpf(1.0f + sqrt_n<float>(1.0f + t));
       dl[a][0] = -q;
-      dl[a][1] = fmaf(-q, dz, dz - q);
-      dl[a][2] = fmaf(-q, dzi, dzi - q);
+      dl[a][1] = fmaf(3.0f, ua, 2.0f * q);
+      dl[a][2] = fmaf(-3.0f, ua, 2.0f * q);
       v.u[a] = ua;
     } else {
       dl[a][0] = dl[a][1] = dl[a][2] = 0.0f;
@@ -1266,12 +1285,10 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
       const float sn = fmaf(ab, seqi - si, si);
       tmin = fminf(tmin, v.r + sn);
       T out;
-      if constexpr (S::dev) {
+      if constexpr (S::dev)
         out = T(sn);
-      } else {
-        const float W = SiteDev<D, S>::weight_of(i);
-        out = T(fmaf(W, sn, W * v.r));
-      }
+      else
+        out = SiteDev<D, S>::enc_f(SiteDev<D, S>::weight_of(i), SiteDev<D, S>::weight_lo(i), v.r, sn);
       st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, out);
     }
     return record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag);

@@ -48,6 +48,27 @@ def test_equilibrium_is_the_constrained_entropy_minimiser(orc, D):
         np.testing.assert_allclose(u2, u[:D], rtol=0, atol=2e-15)
 
 
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_equilibrium_per_axis_closed_form(orc, D):
+    """The tensor-product equilibrium is rho prod_a phi_a(c_ia) with the
+    D1Q3 factors phi(0) = (2/3)(2 - s), phi(+-1) = (1/6)(2s - 1 +- 3u),
+    s = sqrt(1 + 3u^2): the moment conditions of the one-dimensional minimiser
+    solved directly (phi(0) + phi(1) + phi(-1) = 1, phi(1) - phi(-1) = u,
+    phi(1) phi(-1) = phi(0)^2 / 16 from stationarity), a form independent of
+    the A z^c product the oracle evaluates."""
+    c, W = orc.lattice(D)
+    rng = np.random.default_rng(7 + D)
+    for _ in range(30):
+        rho = 0.5 + rng.random()
+        u = 0.6 * (2 * rng.random(3) - 1)
+        s = np.sqrt(1.0 + 3.0 * u * u)
+        phi = {0: 2.0 / 3.0 * (2.0 - s), 1: (2.0 * s - 1.0 + 3.0 * u) / 6.0,
+               -1: (2.0 * s - 1.0 - 3.0 * u) / 6.0}
+        want = np.array([rho * np.prod([phi[int(c[i, a])][a] for a in range(D)])
+                         for i in range(len(W))])
+        np.testing.assert_allclose(orc.equilibrium(D, rho, u[:D]), want, rtol=4e-15, atol=0)
+
+
 def test_equilibrium_against_mpmath_minimiser(orc):
     for D in (2, 3):
         u = [0.17, -0.08, 0.3][:D]
