@@ -359,17 +359,17 @@ struct Site {
 // sum_i W_i c_i = 0:
 //   rho = rho_ref + dr, dr = sum_i W_i s_i;  rho u = sum_i W_i c_i s_i.
 // The equilibrium's per-axis factors A_a z_a^c are written 1 + dl_a(c).  With
-// s_a = sqrt(1 + 3u^2) and q = s_a - 1 = 3u^2 / (1 + s_a) (no cancellation),
-// the factors are A = 1 - q and A z^(+-1) = 2 s_a - 1 +- 3u (expand
-// (1 - q)(1 + 2u + q) - (1 - u) and use q^2 + 2q = 3u^2), so
+// s_a = sqrt(1 + 3u^2) and q = s_a - 1 = 3u^2 / (1 + s_a) (no cancellation)
+// they are A = 1 - q and A z^(+-1) = 2 s_a - 1 +- 3u (expand
+// (1 - q)(1 + 2u + q) - (1 - u) and use q^2 + 2q = 3u^2):
 //   dl(0) = -q,   dl(+-1) = 2q +- 3u,
-// one rounding each; sum_c w(c) dl(c) = 0 and sum_c w(c) c dl(c) = u then
-// hold up to those roundings; then f^eq_i / W_i = rho (1 + Dl_i), Dl_i = prod_a (1 + dl_a) - 1 expanded
-// pairwise, and s^eq_i = dr + rho Dl_i.  The entropy differences and alpha
-// are evaluated in FP64 from
-//   x_i = f_i / f^eq_i - 1 = (s_i - s^eq_i) / (rho_ref + s^eq_i)
-// and f^eq_i = W_i (rho_ref + s^eq_i), and the collision (Eq. (1)) is
-//   s~_i = s_i + alpha beta (s^eq_i - s_i).
+// one rounding each, so that sum_c w(c) dl(c) = 0 and sum_c w(c) c dl(c) = u
+// hold up to those roundings.  Then f^eq_i / W_i = rho (1 + Dl_i) with
+// Dl_i = prod_a (1 + dl_a) - 1 expanded pairwise, s^eq_i = dr + rho Dl_i,
+// and the entropy differences and alpha are evaluated in FP64 from
+//   x_i = f_i / f^eq_i - 1 = (s_i - s^eq_i) / (rho_ref + s^eq_i),
+//   f^eq_i = W_i (rho_ref + s^eq_i);
+// the collision (Eq. (1)) is s~_i = s_i + alpha beta (s^eq_i - s_i).
 template <int D, class S>
 struct SiteDev {
   using L = Lattice<D>;
@@ -418,6 +418,8 @@ struct SiteDev {
   __device__ __forceinline__ double fe(int i, const Pass& p) const {
     return double(float(L::W(i)) * (r + seq(i, p)));
   }
+  // x_i to FP32 relative accuracy (the reciprocal is the hardware one, 1 ulp):
+  // its absolute error is that of s_i - s^eq_i, O(|u|) times FP32 rounding
   __device__ __forceinline__ double x(int i, const Pass& p) const {
     const float q = seq(i, p);
     return double((s(i) - q) * __builtin_amdgcn_rcpf(r + q));

@@ -50,13 +50,16 @@ MIX = [  # (D, shape, steps, kwargs)
     (2, (50, 50, 1), 333, dict(storage="f32", beta=0.96, mode="secant")),
     (19, (14, 10, 9), 50, dict(storage="f32", beta=0.98)),
     (19, (16, 16, 16), 80, dict(storage="f16dev", beta=0.99)),
+    (2, (64, 48, 1), 100, dict(storage="f16dev", beta=0.99, fp64="mixed")),
+    (3, (16, 16, 8), 40, dict(storage="f32dev", beta=0.98, fp64="mixed")),
 ]
 
 
 def test_server_mix_equals_alone(gpu):
-    """Fourteen requests of mixed lattices, sizes, storages, modes and step
-    counts, arriving while earlier ones run (5 slots, 37-step rounds): the
-    final rho, u of each equal those of the same simulation advanced alone."""
+    """Sixteen requests of mixed lattices, sizes, storages, alpha modes, site
+    arithmetic and step counts, arriving while earlier ones run (5 slots,
+    37-step rounds): the final rho, u of each equal those of the same
+    simulation advanced alone."""
     dev = torch.device("cuda")
     stream = torch.cuda.Stream()
     fields = [_fields(D, shp, 100 + k) for k, (D, shp, _, _) in enumerate(MIX)]
