@@ -137,6 +137,28 @@ def mp_G(D: int, f, alpha, dps: int = 50) -> mp.mpf:
         return mp_H(fs, W) - mp_H(fm, W)
 
 
+def mp_alpha_closed(D: int, f, dps: int = 60) -> mp.mpf:
+    """The closed-form alpha in mpmath: alpha_* = min(2, alpha_max)
+    (Eq. (8), alpha_max = 1 + 1 / max_i x_i over x_i > 0), accepted when
+    H(f*(alpha_*)) <= H(f), else Eq. (9) clipped to [1, alpha_*]; the
+    equilibrium from the multiplier minimisation, f taken exactly as given."""
+    with mp.workdps(dps):
+        fm = [mp.mpf(float(v)) for v in f]
+        rho = sum(fm)
+        c = abi_velocities(D)
+        u = [sum(fm[i] * int(c[i, a]) for i in range(len(fm))) / rho for a in range(dim(D))]
+        feq = mp_lagrange_equilibrium(D, rho, u, dps)
+        W = mp_weights(D)
+        xmax = max(fm[i] / feq[i] - 1 for i in range(len(fm)))
+        astar = mp.mpf(2) if xmax <= 1 else 1 + 1 / xmax
+        fs = [fm[i] + astar * (feq[i] - fm[i]) for i in range(len(fm))]
+        Hs, H0, He = mp_H(fs, W), mp_H(fm, W), mp_H(feq, W)
+        Gs, Ds = Hs - H0, Hs - He
+        if Gs <= 0:
+            return astar
+        return min(max(astar + Gs / Ds * (1 - astar), mp.mpf(1)), astar)
+
+
 def mp_root(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
     """Nontrivial root of G on [lo, hi] by mpmath bisection (G(lo) <= 0 < G(hi))."""
     with mp.workdps(dps):

@@ -426,6 +426,49 @@ def test_full_size_d3q27_512_sampled(gpu, orc):
     torch.cuda.empty_cache()
 
 
+def test_full_size_d2q9_shear_1024(gpu, orc):
+    """The 1024^2 FP32 shear layer (u0 = 0.04, kappa = 80, delta = 0.05,
+    Re = 3e4) after 200 steps: one more step over the whole grid against the
+    oracle from the GPU's decoded pre-state.  Populations to one FP32
+    rounding; the counts of sites with alpha < 2 and with accepted alpha = 2
+    to within 2 (a tier decision at rounding level can go either way).
+    Alpha: here |x_i| ~ 1e-6 .. 1e-4 and 2 - alpha ~ |x| / 3.  The oracle
+    forms G(2) = sum f^eq [phi(-x) - phi(x)] ~ sum f^eq x^3 / 3 from phi
+    values that each carry about eps |x| of rounding, so its alpha is good
+    to about eps / |x| ~ eps / (3 (2 - alpha)); the kernel's series has no
+    such cancellation.  So alpha is compared with the oracle to
+    1e-12 + 10 eps / (2 - alpha), and on 24 sites with a 60-digit evaluation
+    of Eqs. (8)-(9) to 1e-14."""
+    n = 1024
+    beta = Wk.shear_beta(n)
+    rho, u = Wk.shear_layer(n)
+    sim = _sim(gpu, 2, (n, n, 1), rho=rho, u=u, storage="f32", beta=beta,
+               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS)
+    sim.step(200)
+    pre = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    st = sim.stats()
+    sim.close()
+    fo, ao, d = orc.step(_ocfg(orc, 2, (n, n, 1), beta=beta, nthreads=16), pre,
+                         want_alpha=True, want_diag=True)
+    assert np.all(np.abs(fg - fo) <= 2.0 ** -24 * np.abs(fo) * 1.01)
+    eps = 2.0 ** -52
+    cond = 10.0 * eps / np.maximum(2.0 - ao, 1e-300)
+    assert np.all(np.abs(ag - ao) <= 1e-12 + cond)
+    order = np.argsort(2.0 - ag)
+    lt2 = order[(2.0 - ag)[order] > 0]
+    rng = np.random.default_rng(1024)
+    pick = np.unique(np.concatenate([lt2[:8], lt2[-8:], rng.choice(lt2, 8, replace=False)]))
+    for s in pick:
+        am = float(H.mp_alpha_closed(2, pre[:, s]))
+        assert abs(ag[s] - am) <= 1e-14, (s, ag[s], ao[s], am)
+    assert 0 < d["n_alpha_lt2"] < n * n
+    assert abs(st["n_alpha_lt2"] - d["n_alpha_lt2"]) <= 2
+    assert abs(st["n_accept2"] - d["n_accept2"]) <= 2
+
+
 def test_shock_tube_d1q3_alpha_field(gpu, orc):
     """D1Q3 shock tube run to t = 500 on the GPU (FP64 storage): populations
     and the alpha field of the next step match the oracle."""
