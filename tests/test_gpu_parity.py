@@ -402,14 +402,16 @@ def test_init_rejects_invalid_fields(gpu):
         gpu.Simulation(2, 16, 16, 1, rho0=rho, u0=u)
 
 
-def test_full_size_d3q27_512_sampled(gpu, orc):
+@pytest.mark.parametrize("n,storage", [(512, "f32"), (256, "f16dev")])
+def test_full_size_d3q27_sampled(gpu, orc, n, storage):
     """The 512^3 FP32 Taylor-Green box in the benchmark's launch
-    configuration: one step checked site by site against the oracle at 2048
-    sampled sites (the oracle collides the GPU's own decoded pre-state)."""
-    n = 512
+    configuration, and the 256^3 box of the precision sweep with FP16
+    deviation storage: one step checked site by site against the oracle at
+    2048 sampled sites (the oracle collides the GPU's own decoded pre-state);
+    one rounding of the output into the storage format."""
     b = Wk.tgv3d_beta(n)
     rho, u = Wk.taylor_green_3d(n)
-    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage="f32", beta=b)
+    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage=storage, beta=b)
     del rho, u
     sim.step(3)
     rng = np.random.default_rng(512)
@@ -419,9 +421,14 @@ def test_full_size_d3q27_512_sampled(gpu, orc):
     sim.step(1)
     post = sim.gather(sites, 1).cpu().numpy()
     cfg = orc.Config(D=3, nx=1, beta=b)
+    W = H.textbook_weights(3)
     for k in range(sites.size):
         ft, _ = orc.collide_site(cfg, pre[:, k])
-        assert np.all(np.abs(post[:, k] - ft) <= 2.0 ** -24 * np.abs(ft) * 1.01), sites[k]
+        if storage == "f32":
+            tol = 2.0 ** -24 * np.abs(ft) * 1.01
+        else:
+            tol = W * (2.0 ** -11 * np.abs(ft / W - 1.0) * 1.01 + 2.0 ** -24)
+        assert np.all(np.abs(post[:, k] - ft) <= tol), sites[k]
     sim.close()
     torch.cuda.empty_cache()
 
