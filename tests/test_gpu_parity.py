@@ -318,6 +318,26 @@ def test_mixed_arithmetic_taylor_green_2d(gpu, orc, storage, tol, mtol):
     sim.close()
 
 
+def test_mixed_arithmetic_taylor_green_3d(gpu, orc):
+    """Mixed arithmetic on the D3Q27 Taylor-Green vortex, 24^3, FP32
+    deviation storage, 300 steps: velocity within 1e-4 of the FP64 oracle
+    relative to its maximum, total mass within 5e-6 (three axes of
+    equilibrium deviations, each normalised up to about 2.5e-9 of rho per
+    step, times alpha beta ~ 2 and 300 steps)."""
+    n, steps = 24, 300
+    b = Wk.tgv3d_beta(n)
+    rho, u = Wk.taylor_green_3d(n)
+    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage="f32dev", beta=b, fp64="mixed")
+    sim.step(steps)
+    rg, ug = sim.moments()
+    cfg = _ocfg(orc, 3, (n, n, n), beta=b, nthreads=16)
+    fo, _, _ = orc.run(cfg, orc.init(cfg, rho, u), steps)
+    ro, uo = orc.moments(cfg, fo)
+    assert np.max(np.abs(ug.cpu().numpy() - uo)) / np.max(np.abs(uo)) <= 1e-4
+    assert abs(float(rg.sum()) - float(ro.sum())) <= 5e-6 * float(ro.sum())
+    sim.close()
+
+
 def test_d3q27_multistep_fp64_ragged(gpu, orc):
     shape = (24, 20, 18)
     N = int(np.prod(shape))
