@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM roofline, closed-form vs Newton α; p50/p99 batched latency"
 HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}
+# site arithmetic: (dtype of the JSON line, description)
+ARITH = {"fp64": ("f64", "FP64"), "mixed": ("f32+f64", "mixed (FP32 on deviations, FP64 alpha)"),
+         "fp32": ("f32", "FP32")}
 
 
 def log(msg: str) -> None:
@@ -67,10 +70,10 @@ def measured_traffic(workload_key: str):
     return rec.get("bytes_per_launch")
 
 
-def time_mode(elbm, torch, n, storage, beta, mode, steps, warmup, diag, rho, u):
+def time_mode(elbm, torch, n, storage, beta, mode, steps, warmup, diag, rho, u, arith="fp64"):
     sim = elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, device="cuda:0",
                           storage=storage, beta=beta, mode=mode, diag=diag,
-                          root_max_iter=200)
+                          root_max_iter=200, fp64=arith)
     stream = sim.stream
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -199,6 +202,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES))
+    ap.add_argument("--arith", default="fp64", choices=sorted(ARITH),
+                    help="site arithmetic: fp64 (default), or for the closed form mixed "
+                         "(FP32 on the deviations, FP64 alpha) or fp32")
     ap.add_argument("--compare-steps", type=int, default=10)
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,6 +220,10 @@ def main() -> int:
                     help="also run one device copy of this many MiB (a known-size kernel "
                          "that calibrates hardware byte counters in profiling runs)")
     args = ap.parse_args()
+    if args.arith != "fp64" and args.only != "closed":
+        print("--arith mixed / fp32 is built for the closed form: add --only closed",
+              file=sys.stderr)
+        return 2
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -252,7 +262,8 @@ def main() -> int:
         steps = args.steps if mode in ("closed", "bgk") else args.compare_steps
         warm = args.warmup if mode in ("closed", "bgk") else 2
         log(f"{mode}: warmup {warm}, timing {steps} steps")
-        ms, wall, st = time_mode(elbm, torch, n, storage, beta, mode, steps, warm, diag, rho, u)
+        ms, wall, st = time_mode(elbm, torch, n, storage, beta, mode, steps, warm, diag, rho, u,
+                                 args.arith)
         results[mode] = dict(ms=ms, wall=wall, stats=st, steps=steps)
         log(f"{mode}: {ms:.3f} ms/step, {N / ms / 1e3:.0f} MLUPS")
     del rho, u
@@ -264,7 +275,7 @@ def main() -> int:
     Q, b = 27, BYTES[storage]
     alg_bytes = 2 * Q * b * N  # read + write every population once per step
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    key = f"d3q27_{n}_{storage}_{main_mode}"
+    key = f"d3q27_{n}_{storage}_{main_mode}" + ("" if args.arith == "fp64" else f"_{args.arith}")
     traffic = measured_traffic(key)
     out = {
         "metric": METRIC,
@@ -277,18 +288,20 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": ARITH[args.arith][0],
         "data": "synthetic (analytic Taylor-Green initial field)",
         "config": {"workload": f"D3Q27 ELBM Taylor-Green vortex {n}^3 periodic, "
-                               f"{storage.upper()} population storage, FP64 site arithmetic, "
+                               f"{storage.upper()} population storage, {ARITH[args.arith][1]} site "
+                               f"arithmetic, "
                                f"u0=0.05, Re=1600, {main_mode} alpha",
                    "lattice": "D3Q27", "n": n, "sites": N, "storage": storage,
-                   "beta": beta, "alpha_mode": main_mode, "diagnostics": "counts"},
+                   "beta": beta, "alpha_mode": main_mode, "arithmetic": args.arith,
+                   "diagnostics": "counts"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": f"k_step<3,Store{storage},{main_mode}>"},
+                     "kernel": f"k_step<3,Store{storage},{main_mode},{args.arith}>"},
     }
     st = r["stats"]
     if st:
