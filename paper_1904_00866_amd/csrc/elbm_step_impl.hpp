@@ -1026,16 +1026,7 @@ __device__ __forceinline__ void site_prepare(Site<D, S, R>& v, const SimDesc& d,
 // Arithmetic policies: R = double (all FP64) or float (all FP32) is the
 // site arithmetic itself; Mixed runs FP32 arithmetic on the deviations
 // (SiteDev) and evaluates the entropy differences and alpha in FP64.
-// SiteReal names the type of the alpha evaluation.
 struct Mixed {};
-template <class P>
-struct SiteReal {
-  using type = P;
-};
-template <>
-struct SiteReal<Mixed> {
-  using type = double;
-};
 template <class P>
 constexpr bool kIsMixed = std::is_same<P, Mixed>::value;
 
@@ -1135,51 +1126,56 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
   return flags;
 }
 
-// One site from its pulled populations: moments, equilibrium, alpha,
-// collision, store of dst_i(x) at the site's own index.  `live` is false for
-// the padding lanes of the last tile: they compute on the values of site 0
-// (so that wavefront-wide votes see ordinary numbers) and store into the
-// padding blocks past N, which every buffer has up to the next whole tile
-// and which no step reads.
-//
-// PHASE (closed form): kPhaseCommon leaves the lanes that need the rare
-// tier untouched and returns true for them; site_update_rare completes them.
-template <int D, class S, int MODE, class AP, bool SUMS, int PHASE = kPhaseAll>
-__device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename S::T* __restrict__ src,
-                                            typename S::T* __restrict__ dst, uint32_t s,
-                                            bool live, const typename S::T (&raw)[Lattice<D>::Q],
-                                            Acc& acc, int diag) {
+// The mixed policy's site update (closed form): FP32 arithmetic on the
+// deviations (SiteDev), the entropy differences and alpha in FP64.
+template <int D, class S, int MODE, bool SUMS, int PHASE>
+__device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
+                                                const typename S::T* __restrict__ src,
+                                                typename S::T* __restrict__ dst, uint32_t s,
+                                                bool live,
+                                                const typename S::T (&raw)[Lattice<D>::Q],
+                                                Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
-  using R = typename SiteReal<AP>::type;  // arithmetic of the site type
+  constexpr uint32_t es = sizeof(T);
+  const uint32_t sl = live ? s : 0u;
+  SiteDev<D, S> v;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+  double j[3];
+  site_prepare_dev(v, d, src, sl, j);
+  const AlphaOut<double> ao = choose_alpha<MODE, PHASE>(v, d);
+  if (PHASE == kPhaseCommon && ao.deferred) return SiteOut{true, 0u};
+  const float ab = float(ao.alpha * d.beta);
+  const auto P = v.pass_opaque();
+  float tmin = INFINITY;  // min of f~_i / W_i: its sign is that of f~_i
+  const uint32_t lo = (s & 63u) * es;
+  const gaddr blk = block_base<Q>(dst, s);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float si = v.s(i);
+    const float sn = fmaf(ab, v.seq(i, P) - si, si);
+    if constexpr (PHASE != kPhaseCommon) tmin = fminf(tmin, v.r + sn);
+    st_nt<T>(blk + i * kLane * es, kLane * es, lo, v.enc(i, sn));
+    sched_group(i);
+  }
+  return SiteOut{false, record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag)};
+}
+
+// The site update in FP64 or FP32 site arithmetic (R), every alpha mode.
+template <int D, class S, int MODE, class R, bool SUMS, int PHASE>
+__device__ __forceinline__ SiteOut site_update_fp(const SimDesc& d,
+                                               const typename S::T* __restrict__ src,
+                                               typename S::T* __restrict__ dst, uint32_t s,
+                                               bool live, const typename S::T (&raw)[Lattice<D>::Q],
+                                               Acc& acc, int diag) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  using T = typename S::T;
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;  // the site whose values were loaded
 
-  if constexpr (kIsMixed<AP>) {
-    // the mixed policy (closed form): FP32 on the deviations, FP64 alpha
-    SiteDev<D, S> v;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
-    double j[3];
-    site_prepare_dev(v, d, src, sl, j);
-    const AlphaOut<double> ao = choose_alpha<MODE, PHASE>(v, d);
-    if (PHASE == kPhaseCommon && ao.deferred) return SiteOut{true, 0u};
-    const float ab = float(ao.alpha * d.beta);
-    const auto P = v.pass_opaque();
-    float tmin = INFINITY;  // min of f~_i / W_i: its sign is that of f~_i
-    const uint32_t lo = (s & 63u) * es;
-    const gaddr blk = block_base<Q>(dst, s);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float si = v.s(i);
-      const float sn = fmaf(ab, v.seq(i, P) - si, si);
-      if constexpr (PHASE != kPhaseCommon) tmin = fminf(tmin, v.r + sn);
-      st_nt<T>(blk + i * kLane * es, kLane * es, lo, v.enc(i, sn));
-      sched_group(i);
-    }
-    return SiteOut{false, record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag)};
-  }
   Site<D, S, R> v;
 #pragma unroll
   for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
@@ -1247,54 +1243,77 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
   }
 }
 
-// A lane deferred by the common phase: the populations are reloaded (from
-// the caches, which this wavefront has just filled), the moments and the
-// equilibrium recomputed by the same arithmetic, alpha taken from the rare
-// tier, and the collision run as a rolled loop that re-reads each
-// population, so no per-direction array stays live across the logarithms.
-template <int D, class S, int MODE, class AP, bool SUMS>
-__device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
-                                                 const typename S::T* __restrict__ src,
-                                                 typename S::T* __restrict__ dst, uint32_t s,
-                                                 bool live, Acc& acc, int diag) {
+// One site from its pulled populations: moments, equilibrium, alpha,
+// collision, store of dst_i(x) at the site's own index.  `live` is false for
+// the padding lanes of the last tile: they compute on the values of site 0
+// (so that wavefront-wide votes see ordinary numbers) and store into the
+// padding blocks past N, which every buffer has up to the next whole tile
+// and which no step reads.
+//
+// PHASE (closed form): kPhaseCommon leaves the lanes that need the rare
+// tier untouched and returns true for them; site_update_rare completes them.
+// AP: the arithmetic policy (double, float or Mixed).
+template <int D, class S, int MODE, class AP, bool SUMS, int PHASE = kPhaseAll>
+__device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename S::T* __restrict__ src,
+                                            typename S::T* __restrict__ dst, uint32_t s,
+                                            bool live, const typename S::T (&raw)[Lattice<D>::Q],
+                                            Acc& acc, int diag) {
+  if constexpr (kIsMixed<AP>)
+    return site_update_dev<D, S, MODE, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
+  else
+    return site_update_fp<D, S, MODE, AP, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
+}
+
+// The rare path of the mixed policy (SiteDev).
+template <int D, class S, int MODE, bool SUMS>
+__device__ __forceinline__ uint32_t site_update_rare_dev(const SimDesc& d, const typename S::T* __restrict__ src,
+    typename S::T* __restrict__ dst, uint32_t s, bool live, Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
   using T = typename S::T;
-  using R = typename SiteReal<AP>::type;
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;
-  if constexpr (kIsMixed<AP>) {
-    SiteDev<D, S> v;
-    if constexpr (Codec<S, double>::kF16) {
-      T raw[Q];
-      load_site<D>(d, src, sl, raw);
+  SiteDev<D, S> v;
+  if constexpr (Codec<S, double>::kF16) {
+    T raw[Q];
+    load_site<D>(d, src, sl, raw);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
-    } else {
-      load_site<D>(d, src, sl, v.raw);
-    }
-    double j[3];
-    site_prepare_dev(v, d, src, sl, j);
-    const AlphaOut<double> ao = choose_alpha<MODE, kPhaseRare>(v, d);
-    const float ab = float(ao.alpha * d.beta);
-    float tmin = INFINITY;
-    const uint32_t lo = (s & 63u) * es;
-    const gaddr blk = block_base<Q>(dst, s);
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-      float si, seqi;
-      v.sq(i, si, seqi);
-      const float sn = fmaf(ab, seqi - si, si);
-      tmin = fminf(tmin, v.r + sn);
-      T out;
-      if constexpr (S::dev)
-        out = T(sn);
-      else
-        out = SiteDev<D, S>::enc_f(SiteDev<D, S>::weight_of(i), SiteDev<D, S>::weight_lo(i), v.r, sn);
-      st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, out);
-    }
-    return record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag);
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+  } else {
+    load_site<D>(d, src, sl, v.raw);
   }
+  double j[3];
+  site_prepare_dev(v, d, src, sl, j);
+  const AlphaOut<double> ao = choose_alpha<MODE, kPhaseRare>(v, d);
+  const float ab = float(ao.alpha * d.beta);
+  float tmin = INFINITY;
+  const uint32_t lo = (s & 63u) * es;
+  const gaddr blk = block_base<Q>(dst, s);
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    float si, seqi;
+    v.sq(i, si, seqi);
+    const float sn = fmaf(ab, seqi - si, si);
+    tmin = fminf(tmin, v.r + sn);
+    T out;
+    if constexpr (S::dev)
+      out = T(sn);
+    else
+      out = SiteDev<D, S>::enc_f(SiteDev<D, S>::weight_of(i), SiteDev<D, S>::weight_lo(i), v.r, sn);
+    st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, out);
+  }
+  return record_site<SUMS>(d, s, live, v, ao, double(tmin), j, acc, diag);
+}
+
+// The rare path in FP64 or FP32 site arithmetic (R).
+template <int D, class S, int MODE, class R, bool SUMS>
+__device__ __forceinline__ uint32_t site_update_rare_fp(const SimDesc& d, const typename S::T* __restrict__ src,
+    typename S::T* __restrict__ dst, uint32_t s, bool live, Acc& acc, int diag) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  using T = typename S::T;
+  constexpr uint32_t es = sizeof(T);
+  const uint32_t sl = live ? s : 0u;
   Site<D, S, R> v;
   if constexpr (Codec<S, R>::kF16) {
     T raw[Q];
@@ -1322,6 +1341,22 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
     st_nt<T>(blk + (uint64_t)i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, invW, v.rho_ref));
   }
   return record_site<SUMS>(d, s, live, v, ao, ftmin, j, acc, diag);
+}
+
+// A lane deferred by the common phase: the populations are reloaded (from
+// the caches, which this wavefront has just filled), the moments and the
+// equilibrium recomputed by the same arithmetic, alpha taken from the rare
+// tier, and the collision run as a rolled loop that re-reads each
+// population, so no per-direction array stays live across the logarithms.
+template <int D, class S, int MODE, class AP, bool SUMS>
+__device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
+                                                 const typename S::T* __restrict__ src,
+                                                 typename S::T* __restrict__ dst, uint32_t s,
+                                                 bool live, Acc& acc, int diag) {
+  if constexpr (kIsMixed<AP>)
+    return site_update_rare_dev<D, S, MODE, SUMS>(d, src, dst, s, live, acc, diag);
+  else
+    return site_update_rare_fp<D, S, MODE, AP, SUMS>(d, src, dst, s, live, acc, diag);
 }
 
 // One workgroup per ELBM_TILES tiles of kBlock consecutive sites; the loads
