@@ -365,6 +365,40 @@ def test_per_site_h_theorem_on_the_gpu(gpu, D, eps, log_uniform):
         assert st["n_alphastar_lt2"] > N // 20
 
 
+@pytest.mark.parametrize("D", [2, 3])
+def test_secant_iterates_on_the_gpu(gpu, D):
+    """The modified secant on the kernel: its first iterate from alpha = 1
+    is Eq. (9) (G(1) = -D exactly), so one iteration reproduces the closed
+    form's alpha; further iterates increase, and where Eq. (9) applied they
+    close in on the root of Eq. (4) (Newton) from below, per site, up to
+    rounding."""
+    shape = SHAPES[D]
+    N = int(np.prod(shape))
+    f0 = Wk.random_populations(H.textbook_weights(D), N, 0.3, 4300 + D, tilt=0.1,
+                               log_uniform_eps=False)
+
+    def alpha(**kw):
+        sim = _sim(gpu, D, shape, f0, storage="f64", beta=0.97, diag=gpu.DIAG_ALPHA, **kw)
+        sim.step(1)
+        a = sim.alpha_field().cpu().numpy()
+        sim.close()
+        return a
+
+    ac = alpha(mode="closed")
+    a1, a2, a4 = (alpha(mode="secant", secant_iters=k) for k in (1, 2, 4))
+    an = alpha(mode="newton")
+    assert np.max(np.abs(a1 - ac)) <= 1e-14
+    for lo, hi in ((ac, a2), (a2, a4)):
+        assert np.all(hi >= lo - 1e-12)
+    # where Eq. (9) was applied and not clamped (1 < alpha < 2 = alpha_*
+    # or alpha_max), the iterates close in on the root; at alpha = 2 the
+    # accepted alpha_* is kept, while the Newton root of Eq. (4) may exceed 2
+    inner = (ac > 1.0) & (ac < 2.0) & (an > ac + 1e-9)
+    assert inner.sum() > N // 20
+    assert np.all(a4[inner] <= an[inner] + 1e-12)
+    assert np.all(np.abs(a4 - an)[inner] < np.abs(ac - an)[inner])
+
+
 def test_d3q27_multistep_fp64_ragged(gpu, orc):
     shape = (24, 20, 18)
     N = int(np.prod(shape))
