@@ -11,9 +11,12 @@ is needed; its parity with the CPU oracle is established by the GPU tests).
     python experiments.py e2     D2Q9 128^2 shear layer, nu = 1e-5, 3200 steps:
                                  proportion of sites accepting alpha = 2
     python experiments.py w4     D3Q27 256^3 Taylor-Green, 2000 steps, storage
-                                 FP64 / FP32 / FP32-dev / FP16-dev under both
-                                 precision policies: velocity and kinetic-energy
-                                 error vs FP64, per-site H increases
+                                 FP64 / FP32 / FP32-dev / FP16-dev under FP64,
+                                 mixed and FP32 site arithmetic: velocity and
+                                 kinetic-energy error vs FP64, per-site H increases
+    python experiments.py w5p    the serving stream (64 requests at 20/s) through
+                                 a server with 8 slots, first come first served
+                                 and with preemption: latency percentiles, MLUPS
     python experiments.py f3     D3Q19 beside D3Q27: 512^3 FP32 step time and
                                  HBM roofline fraction of the closed form, LBGK
                                  and (256^3) Newton; 128^3 Re = 1600 Taylor-Green:
@@ -395,9 +398,38 @@ def f3burg(n3=512, n2=2048, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000,
     return out
 
 
+# -------------------------------------------------------------------- W5p --
+def w5p(n_req=64, rate=20.0, max_active=8, round_steps=50, preempt_rounds=20):
+    """The W5 stream through a server whose slots are the bottleneck, once
+    first come first served and once with preemption (long residents moved
+    out to host memory so that queued requests get in)."""
+    from paper_1904_00866_amd import serving
+    reqs = Wk.serving_stream(n_req, rate=rate)
+    out = {"experiment": "w5p",
+           "workload": f"{n_req} D2Q9 shear-layer requests at {rate}/s (seed 20250101), "
+                       f"{max_active} slots, rounds of {round_steps} steps", "runs": {}}
+    for name, pr in (("fcfs", 0), (f"preempt_{preempt_rounds}", preempt_rounds)):
+        res = serving.run_stream(reqs, max_active=max_active, round_steps=round_steps,
+                                 preempt_rounds=pr, log=log)
+        lat = np.array(res["latency_s"])
+        work = np.array([r["n"] * r["n"] * r["steps"] for r in reqs], dtype=float)
+        small = work <= np.median(work)
+        out["runs"][name] = {
+            "p50_s": res["p50_s"], "p99_s": res["p99_s"], "mean_s": res["mean_s"],
+            "max_s": res["max_s"], "queue_p50_s": res["queue_p50_s"],
+            "queue_p99_s": res["queue_p99_s"], "mlups": res["mlups"], "span_s": res["span_s"],
+            "preemptions": res["preemptions"], "completed": res["completed"],
+            "failed": res["failed"],
+            "p50_smaller_half_s": float(np.percentile(lat[small], 50)),
+            "p50_larger_half_s": float(np.percentile(lat[~small], 50))}
+        log(f"w5p {name}: {out['runs'][name]}")
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "f3", "f3burg"])
+    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "w5p", "f3", "f3burg"])
     ap.add_argument("--w2-steps", type=int, default=20000)
     ap.add_argument("--f3-n", type=int, default=512)
     ap.add_argument("--f3-steps", type=int, default=20)
@@ -415,7 +447,7 @@ def main():
     elbm.lib()
     for w in args.which:
         t0 = time.time()
-        res = {"w1": w1, "e2": e2, "w4": w4,
+        res = {"w1": w1, "e2": e2, "w4": w4, "w5p": w5p,
                "f3burg": lambda: f3burg(n3=args.f3_n, steps=args.f3_steps,
                                         tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
                                         cases=[c for c in args.f3burg_cases.split(",") if c]),

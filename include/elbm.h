@@ -291,6 +291,19 @@ typedef struct {
   void *hip_stream;     /* stream of all server work (NULL = null stream)   */
   int32_t max_active;   /* resident simulations at once, >= 1              */
   int32_t round_steps;  /* steps per scheduling round, >= 1                */
+  int32_t preempt_rounds; /* 0: never preempt.  k >= 1: when the request at
+                           the head of the queue cannot be admitted (no free
+                           slot or no room in the pool), requests resident
+                           for at least k rounds, with more than one round of
+                           steps left and more than twice the head's
+                           remaining work (steps x sites) are preempted, most
+                           remaining work first, if that makes room:
+                           their populations are copied to pinned host
+                           memory (a checkpoint, see elbm_export), their pool
+                           block is freed and they re-enter the queue at the
+                           back; re-admitted, they continue from the
+                           checkpoint bit for bit                            */
+  int32_t reserved;     /* must be 0                                         */
 } elbm_server_config;
 
 typedef struct {
@@ -310,11 +323,11 @@ enum { ELBM_REQ_QUEUED = 0, ELBM_REQ_RUNNING = 1, ELBM_REQ_DONE = 2,
        ELBM_REQ_FAILED = 3 };
 
 typedef struct {
-  int32_t state;        /* ELBM_REQ_*                                        */
-  int32_t reserved;
+  int32_t state;        /* ELBM_REQ_* (a preempted request is QUEUED)        */
+  int32_t preemptions;  /* times the request was preempted                   */
   int64_t steps_done;
   double t_submit;      /* seconds on the server's monotonic clock          */
-  double t_admit;       /* admission (0 while queued)                        */
+  double t_admit;       /* first admission (0 while queued)                  */
   double t_done;        /* completion observed on the host (0 until done)   */
   size_t footprint;     /* pool bytes held while resident                    */
 } elbm_request_info;
@@ -325,6 +338,7 @@ typedef struct {
   int64_t site_updates; /* sum over completed steps of the box sizes         */
   int64_t max_resident; /* most simulations resident at once                 */
   double t_first_submit, t_last_done;
+  int64_t preemptions;  /* requests moved out to host memory (preempt_rounds) */
 } elbm_server_stats;
 
 /* Create a server; starts its scheduler thread on the current device. */

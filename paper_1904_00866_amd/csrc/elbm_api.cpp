@@ -281,6 +281,17 @@ elbm_status init_sim(const elbm_config* cfg, const double* rho0, const double* u
                      void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out,
                      bool validate);
 
+// A simulation over dev_state that continues from a checkpoint held in
+// host memory (pinned, ckpt_bytes == elbm_checkpoint_bytes) at time t: the
+// copy is enqueued on hip_stream, so the host buffer must stay valid until
+// the stream has passed it.  Used by the server to resume a preempted request.
+elbm_status resume_sim(const elbm_config* cfg, void* dev_state, size_t bytes, void* hip_stream,
+                       const void* host_ckpt, size_t ckpt_bytes, int64_t t, elbm_sim** out);
+
+// The current populations (a checkpoint) copied to host memory on the
+// simulation's stream, behind the work already enqueued; *t receives t.
+elbm_status checkpoint_to_host(elbm_sim* sim, void* host_dst, size_t bytes, int64_t* t);
+
 // Free a handle whose stream work the caller knows to be complete (no sync).
 void release_sim(elbm_sim* sim) { delete sim; }
 
@@ -294,6 +305,33 @@ extern "C" elbm_status elbm_init(const elbm_config* cfg, const double* rho0, con
                                  elbm_sim** out) {
   return elbm::init_sim(cfg, rho0, u0, dev_state, bytes, hip_stream, out, true);
 }
+
+namespace {
+// A handle over dev_state for a checked configuration (no device work).
+elbm_sim* new_handle(const elbm_config* cfg, const Layout& L, void* dev_state, void* hip_stream,
+                     int dev) {
+  elbm_sim* s = new (std::nothrow) elbm_sim;
+  if (!s) return nullptr;
+  s->cfg = *cfg;
+  s->L = L;
+  s->base = static_cast<char*>(dev_state);
+  s->buf[0] = s->base + L.off_buf[0];
+  s->buf[1] = s->base + L.off_buf[1];
+  s->cur = 0;
+  s->alpha = reinterpret_cast<double*>(s->base + L.off_alpha);
+  s->counts = s->base + L.off_counts;
+  s->sums = s->base + L.off_sums;
+  s->reduced = reinterpret_cast<Reduced*>(s->base + L.off_misc);
+  s->counter = reinterpret_cast<unsigned long long*>(s->base + L.off_misc + sizeof(Reduced));
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  s->device = dev;
+  s->t = 0;
+  s->have_alpha = s->have_stats = false;
+  s->launch = step_launcher(cfg->lattice, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64,
+                            cfg->entropy);
+  return s;
+}
+}  // namespace
 
 elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const double* u0,
                            void* dev_state, size_t bytes, void* hip_stream, elbm_sim** out,
@@ -313,25 +351,8 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  elbm_sim* s = new (std::nothrow) elbm_sim;
+  elbm_sim* s = new_handle(cfg, L, dev_state, hip_stream, dev);
   if (!s) return fail(ELBM_EINVAL, "out of host memory");
-  s->cfg = *cfg;
-  s->L = L;
-  s->base = static_cast<char*>(dev_state);
-  s->buf[0] = s->base + L.off_buf[0];
-  s->buf[1] = s->base + L.off_buf[1];
-  s->cur = 0;
-  s->alpha = reinterpret_cast<double*>(s->base + L.off_alpha);
-  s->counts = s->base + L.off_counts;
-  s->sums = s->base + L.off_sums;
-  s->reduced = reinterpret_cast<Reduced*>(s->base + L.off_misc);
-  s->counter = reinterpret_cast<unsigned long long*>(s->base + L.off_misc + sizeof(Reduced));
-  s->stream = static_cast<hipStream_t>(hip_stream);
-  s->device = dev;
-  s->t = 0;
-  s->have_alpha = s->have_stats = false;
-  s->launch = step_launcher(cfg->lattice, cfg->storage, cfg->alpha_mode, cfg->alpha_fp64,
-                            cfg->entropy);
 
   const BoxDesc b = box_of(s);
   unsigned long long nbad = 0;
@@ -360,6 +381,56 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
     return hip_fail(e, "elbm_init");
   }
   *out = s;
+  return ELBM_OK;
+}
+
+elbm_status elbm::resume_sim(const elbm_config* cfg, void* dev_state, size_t bytes,
+                             void* hip_stream, const void* host_ckpt, size_t ckpt_bytes,
+                             int64_t t, elbm_sim** out) {
+  if (!out) return fail(ELBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  elbm_status st = check_config(cfg, &L);
+  if (st != ELBM_OK) return st;
+  if (!dev_state || reinterpret_cast<uintptr_t>(dev_state) % kAlign)
+    return fail(ELBM_EINVAL, "dev_state is NULL or not %zu-byte aligned", kAlign);
+  if (bytes < L.total)
+    return fail(ELBM_ENOMEM, "state buffer of %zu bytes, %zu needed", bytes, L.total);
+  if (!host_ckpt || t < 0) return fail(ELBM_EINVAL, "checkpoint is NULL or t < 0");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  elbm_sim* s = new_handle(cfg, L, dev_state, hip_stream, dev);
+  if (!s) return fail(ELBM_EINVAL, "out of host memory");
+  const size_t n = elbm_checkpoint_bytes(s);
+  if (ckpt_bytes != n) {
+    delete s;
+    return fail(ELBM_EINVAL, "checkpoint of %zu bytes, this simulation's is %zu", ckpt_bytes, n);
+  }
+  // every byte of the state defined, as after elbm_init; then the populations
+  if ((e = hipMemsetAsync(s->base, 0, L.off_alpha, s->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s->buf[0], host_ckpt, n, hipMemcpyHostToDevice, s->stream)) !=
+          hipSuccess) {
+    delete s;
+    return hip_fail(e, "resume");
+  }
+  s->t = t;
+  *out = s;
+  return ELBM_OK;
+}
+
+elbm_status elbm::checkpoint_to_host(elbm_sim* s, void* host_dst, size_t bytes, int64_t* t) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  const size_t n = elbm_checkpoint_bytes(s);
+  if (!host_dst || !t) return fail(ELBM_EINVAL, "dst / t is NULL");
+  if (bytes < n) return fail(ELBM_ENOMEM, "checkpoint buffer of %zu bytes, %zu needed", bytes, n);
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  const hipError_t e =
+      hipMemcpyAsync(host_dst, s->buf[s->cur], n, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "checkpoint to host");
+  *t = s->t;
   return ELBM_OK;
 }
 

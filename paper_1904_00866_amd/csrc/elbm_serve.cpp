@@ -6,14 +6,20 @@
 //      two are in flight): finished requests get their completion time, and
 //      the pool blocks of finished, not kept, simulations and of consumed
 //      staging copies return to the free list;
-//   2. admits queued requests first come, first served while a slot is free
+//   2. with preemption enabled (preempt_rounds > 0), moves long-resident
+//      requests out to pinned host memory when that makes room for the
+//      request at the head of the queue (preempt());
+//   3. admits queued requests first come, first served while a slot is free
 //      and the pool has room for state + staging copy of the initial fields:
-//      pinned host copy -> staging block -> f^eq(rho0, u0) in the state;
-//   3. launches one round: up to round_steps steps of every resident
+//      pinned host copy -> staging block -> f^eq(rho0, u0) in the state; a
+//      preempted request needs only its state block and continues from its
+//      checkpoint;
+//   4. launches one round: up to round_steps steps of every resident
 //      simulation, one batched launch per step for each group of residents
 //      that share a kernel (lattice, storage, alpha mode, arithmetic), then
 //      the final moments of the requests that finish, then an event.
-// With two rounds in flight the host work of 1-2 overlaps the GPU.
+// With two rounds in flight the host work of 1-3 overlaps the GPU.  All
+// device work runs on one stream, in order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,6 +47,9 @@ elbm_status init_sim(const elbm_config* cfg, const double* rho0, const double* u
                      bool validate);
 void release_sim(elbm_sim* sim);
 elbm_status set_error(elbm_status st, const char* msg);
+elbm_status resume_sim(const elbm_config* cfg, void* dev_state, size_t bytes, void* hip_stream,
+                       const void* host_ckpt, size_t ckpt_bytes, int64_t t, elbm_sim** out);
+elbm_status checkpoint_to_host(elbm_sim* sim, void* host_dst, size_t bytes, int64_t* t);
 }  // namespace elbm
 
 using elbm::set_error;
@@ -116,6 +125,12 @@ struct Req {
   size_t off = 0;  // state block in the pool
   Pinned host;     // rho0 then u0, until staged
   elbm_sim* sim = nullptr;
+  bool admitted = false;     // admitted at least once
+  int64_t rounds = 0;        // rounds launched since the last admission
+  int32_t preemptions = 0;
+  Pinned ckpt;               // populations while preempted, until resumed
+  size_t ckpt_bytes = 0;
+  int64_t ckpt_t = 0;
 };
 
 // Work enqueued on the stream, and what to do once the GPU has passed it.
@@ -229,7 +244,7 @@ void admit(elbm_server* s, std::unique_lock<std::mutex>& lk) {
     Req* r = s->queue.front();
     size_t off = 0, soff = 0;
     if (!s->pool->alloc(r->state_bytes, &off)) break;
-    if (!s->pool->alloc(r->stage_bytes, &soff)) {
+    if (!r->ckpt.p && !s->pool->alloc(r->stage_bytes, &soff)) {
       s->pool->release(off, r->state_bytes);
       break;
     }
@@ -244,11 +259,17 @@ void admit(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   lk.unlock();
   for (size_t k = 0; k < take.size(); ++k) {
     Req* r = take[k].r;
-    double* stage = reinterpret_cast<double*>(s->base + take[k].soff);
-    const size_t nbytes = size_t(r->N) * (1 + lattice_dim(r->cfg.lattice)) * sizeof(double);
-    if (hipMemcpyAsync(stage, r->host.p, nbytes, hipMemcpyHostToDevice, s->stream) == hipSuccess)
-      st[k] = elbm::init_sim(&r->cfg, stage, stage + r->N, s->base + r->off, r->state_bytes,
-                             s->stream, &r->sim, false);
+    if (r->ckpt.p) {
+      st[k] = elbm::resume_sim(&r->cfg, s->base + r->off, r->state_bytes, s->stream, r->ckpt.p,
+                               r->ckpt_bytes, r->ckpt_t, &r->sim);
+    } else {
+      double* stage = reinterpret_cast<double*>(s->base + take[k].soff);
+      const size_t nbytes = size_t(r->N) * (1 + lattice_dim(r->cfg.lattice)) * sizeof(double);
+      if (hipMemcpyAsync(stage, r->host.p, nbytes, hipMemcpyHostToDevice, s->stream) ==
+          hipSuccess)
+        st[k] = elbm::init_sim(&r->cfg, stage, stage + r->N, s->base + r->off, r->state_bytes,
+                               s->stream, &r->sim, false);
+    }
     any_failed |= st[k] != ELBM_OK;
   }
   // nothing of a failed admission may still be in use on the stream
@@ -257,20 +278,34 @@ void admit(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   const double t = now_s() - s->t0;
   for (size_t k = 0; k < take.size(); ++k) {
     Req* r = take[k].r;
+    const bool resumed = r->ckpt.p != nullptr;
     if (st[k] != ELBM_OK) {
       s->pool->release(r->off, r->state_bytes);
-      s->pool->release(take[k].soff, r->stage_bytes);
-      recycle_pinned(s, r->host);
-      r->host = Pinned{};
+      if (resumed) {
+        recycle_pinned(s, r->ckpt);
+        r->ckpt = Pinned{};
+      } else {
+        s->pool->release(take[k].soff, r->stage_bytes);
+        recycle_pinned(s, r->host);
+        r->host = Pinned{};
+      }
       fail_req(s, r);
       continue;
     }
     r->state = ELBM_REQ_RUNNING;
-    r->t_admit = t;
+    if (!r->admitted) r->t_admit = t;
+    r->admitted = true;
+    r->rounds = 0;
     s->active.push_back(r);
-    s->pending.staging.push_back({take[k].soff, r->stage_bytes});
-    s->pending.pinned.push_back(r->host);
-    r->host = Pinned{};
+    if (resumed) {
+      // the host checkpoint is read by the copy just enqueued
+      s->pending.pinned.push_back(r->ckpt);
+      r->ckpt = Pinned{};
+    } else {
+      s->pending.staging.push_back({take[k].soff, r->stage_bytes});
+      s->pending.pinned.push_back(r->host);
+      r->host = Pinned{};
+    }
   }
   s->stats.max_resident = std::max<int64_t>(s->stats.max_resident, (int64_t)s->active.size());
 }
@@ -344,6 +379,7 @@ void launch_round(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   std::vector<Req*> still;
   for (size_t k = 0; k < act.size(); ++k) {
     act[k]->done += todo[k];
+    act[k]->rounds++;
     if (fin[k])
       rd.finished.push_back(act[k]);
     else
@@ -387,6 +423,92 @@ void retire_oldest(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   s->cv.notify_all();
 }
 
+// Preemption (preempt_rounds > 0; see elbm_server_config).  A resident is
+// preempted only for a queue head with less than half its remaining work
+// (steps x sites), so that long arrivals never evict and residents do not
+// rotate under overload.  A victim's
+// populations are copied to pinned host memory by a copy enqueued behind its
+// last step; since every later use of its pool block (another request's
+// staging or state) is enqueued after that copy on the same stream, the block
+// returns to the free list at once.  Victims are chosen only if freeing their
+// blocks (tried on a copy of the free list) lets the head of the queue in.
+void preempt(elbm_server* s, std::unique_lock<std::mutex>& lk) {
+  if (s->cfg.preempt_rounds <= 0 || s->broken || s->queue.empty()) return;
+  const Req* head = s->queue.front();
+  const size_t head_stage = head->ckpt.p ? 0 : head->stage_bytes;
+  auto fits = [&](Pool pool, size_t resident) {  // on a copy of the free list
+    size_t off = 0;
+    return resident < size_t(s->cfg.max_active) && pool.alloc(head->state_bytes, &off) &&
+           (head_stage == 0 || pool.alloc(head_stage, &off));
+  };
+  if (fits(*s->pool, s->active.size())) return;
+  // only for a head with much less work left than the victim (shortest
+  // remaining work first, with a factor 2 against needless swaps)
+  const int64_t head_work = (head->nsteps - head->done) * head->N;
+  std::vector<Req*> cand;
+  for (Req* r : s->active)
+    if (r->rounds >= s->cfg.preempt_rounds && r->nsteps - r->done > s->cfg.round_steps &&
+        (r->nsteps - r->done) * r->N > 2 * head_work)
+      cand.push_back(r);
+  std::stable_sort(cand.begin(), cand.end(), [](const Req* a, const Req* b) {
+    return (a->nsteps - a->done) * a->N > (b->nsteps - b->done) * b->N;
+  });
+  Pool trial = *s->pool;
+  size_t nv = 0;
+  bool room = false;
+  while (nv < cand.size() && !room) {
+    trial.release(cand[nv]->off, cand[nv]->state_bytes);
+    ++nv;
+    room = fits(trial, s->active.size() - nv);
+  }
+  if (!room) return;
+  cand.resize(nv);
+  std::vector<Req*> still;
+  for (Req* r : s->active)
+    if (std::find(cand.begin(), cand.end(), r) == cand.end()) still.push_back(r);
+  s->active.swap(still);
+  // the copies run with the lock released (see admit)
+  std::vector<Pinned> buf(nv);
+  std::vector<size_t> nb(nv, 0);
+  std::vector<int64_t> tk(nv, 0);
+  std::vector<elbm_status> st(nv, ELBM_EDEVICE);
+  lk.unlock();
+  for (size_t k = 0; k < nv; ++k) {
+    const size_t n = nb[k] = elbm_checkpoint_bytes(cand[k]->sim);
+    buf[k] = take_pinned(s, n);
+    if (!buf[k].p) {
+      void* q = nullptr;
+      if (hipHostMalloc(&q, n, hipHostMallocDefault) == hipSuccess) {
+        buf[k].p = static_cast<double*>(q);
+        buf[k].bytes = n;
+      }
+    }
+    if (buf[k].p) st[k] = elbm::checkpoint_to_host(cand[k]->sim, buf[k].p, n, &tk[k]);
+  }
+  lk.lock();
+  for (size_t k = 0; k < nv; ++k) {
+    Req* r = cand[k];
+    if (st[k] != ELBM_OK) {
+      // the server stops here: the victim is failed with the residents
+      mark_broken(s, std::string("preemption: ") + elbm_last_error());
+      if (buf[k].p) r->ckpt = buf[k];  // freed by elbm_server_destroy after the stream
+      s->active.push_back(r);
+      continue;
+    }
+    s->pool->release(r->off, r->state_bytes);
+    elbm::release_sim(r->sim);
+    r->sim = nullptr;
+    r->ckpt = buf[k];
+    r->ckpt_bytes = nb[k];
+    r->ckpt_t = tk[k];
+    r->state = ELBM_REQ_QUEUED;
+    r->rounds = 0;
+    r->preemptions++;
+    s->stats.preemptions++;
+    s->queue.push_back(r);
+  }
+}
+
 void worker_main(elbm_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -422,6 +544,8 @@ void worker_main(elbm_server* s) {
       seen = s->kick;
       continue;
     }
+    preempt(s, lk);
+    if (s->broken) continue;
     admit(s, lk);
     if (s->broken) continue;
     if (!s->active.empty()) {
@@ -468,6 +592,8 @@ elbm_status elbm_server_create(const elbm_server_config* cfg, elbm_server** out)
     return set_error(ELBM_EINVAL, "server pool must be 256-byte aligned");
   if (cfg->max_active < 1 || cfg->round_steps < 1)
     return set_error(ELBM_EINVAL, "max_active and round_steps must be >= 1");
+  if (cfg->preempt_rounds < 0 || cfg->reserved != 0)
+    return set_error(ELBM_EINVAL, "preempt_rounds < 0 or reserved != 0");
   auto* s = new (std::nothrow) elbm_server;
   if (!s) return set_error(ELBM_EINVAL, "out of host memory");
   s->cfg = *cfg;
@@ -557,6 +683,7 @@ elbm_status elbm_server_poll(elbm_server* s, int64_t id, elbm_request_info* info
   if (!r) return set_error(ELBM_EINVAL, "unknown request id");
   std::memset(info, 0, sizeof *info);
   info->state = r->state;
+  info->preemptions = r->preemptions;
   info->steps_done = r->done;  // steps enqueued so far
   info->t_submit = r->t_submit;
   info->t_admit = r->t_admit;
@@ -632,6 +759,7 @@ elbm_status elbm_server_destroy(elbm_server* s) {
     Req* r = kv.second.get();
     if (r->sim) elbm::release_sim(r->sim);
     if (r->host.p) (void)hipHostFree(r->host.p);
+    if (r->ckpt.p) (void)hipHostFree(r->ckpt.p);
   }
   for (auto& p : s->pinned_cache) (void)hipHostFree(p.p);
   for (hipEvent_t ev : s->spare_events) (void)hipEventDestroy(ev);

@@ -68,7 +68,8 @@ class Stats(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("hip_stream", C.c_void_p),
-                ("max_active", C.c_int32), ("round_steps", C.c_int32)]
+                ("max_active", C.c_int32), ("round_steps", C.c_int32),
+                ("preempt_rounds", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -78,7 +79,7 @@ class Request(C.Structure):
 
 
 class RequestInfo(C.Structure):
-    _fields_ = [("state", C.c_int32), ("reserved", C.c_int32), ("steps_done", C.c_int64),
+    _fields_ = [("state", C.c_int32), ("preemptions", C.c_int32), ("steps_done", C.c_int64),
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
                 ("footprint", C.c_size_t)]
 
@@ -87,7 +88,7 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("rounds", C.c_int64), ("launches", C.c_int64), ("site_updates", C.c_int64),
                 ("max_resident", C.c_int64), ("t_first_submit", C.c_double),
-                ("t_last_done", C.c_double)]
+                ("t_last_done", C.c_double), ("preemptions", C.c_int64)]
 
 
 _lib = None
@@ -323,7 +324,8 @@ class Server:
     work runs on `stream`."""
 
     def __init__(self, pool_bytes: int, *, max_active: int = 64, round_steps: int = 50,
-                 device="cuda", stream: Optional[torch.cuda.Stream] = None):
+                 preempt_rounds: int = 0, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
         self.device = torch.device(device)
         self.stream = stream or torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
@@ -331,7 +333,7 @@ class Server:
             torch.cuda.synchronize(self.device)
             sc = ServerConfig(C.c_void_p(self.pool.data_ptr()), int(pool_bytes),
                               C.c_void_p(self.stream.cuda_stream), int(max_active),
-                              int(round_steps))
+                              int(round_steps), int(preempt_rounds), 0)
             h = C.c_void_p()
             _check(lib().elbm_server_create(C.byref(sc), C.byref(h)))
         self.handle = h
@@ -357,7 +359,8 @@ class Server:
         i = RequestInfo()
         _check(lib().elbm_server_poll(self.handle, int(rid), C.byref(i)))
         return dict(state=REQ_STATES[i.state], steps_done=i.steps_done, t_submit=i.t_submit,
-                    t_admit=i.t_admit, t_done=i.t_done, footprint=i.footprint)
+                    t_admit=i.t_admit, t_done=i.t_done, footprint=i.footprint,
+                    preemptions=i.preemptions)
 
     def wait(self, rid: int, timeout: float = -1.0):
         _check(lib().elbm_server_wait(self.handle, int(rid), float(timeout)))

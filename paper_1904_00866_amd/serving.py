@@ -28,13 +28,14 @@ def footprint(req: dict) -> int:
 
 
 def run_stream(reqs, *, pool_bytes: Optional[int] = None, max_active: int = 64,
-               round_steps: int = 50, keep: tuple = (), realtime: bool = True,
-               device: str = "cuda", log=None) -> dict:
+               round_steps: int = 50, preempt_rounds: int = 0, keep: tuple = (),
+               realtime: bool = True, device: str = "cuda", log=None) -> dict:
     """Serve `reqs` (workloads.serving_stream) and return the measurements.
 
     keep: request indices whose final rho/u are returned (for comparisons
     with alone runs).  pool_bytes defaults to twice the largest footprint
-    times max_active, capped at 64 GiB."""
+    times max_active, capped at 64 GiB.  preempt_rounds: the server's
+    preemption setting (0: first come, first served)."""
     dev = torch.device(device)
     fields = {n: Wk.shear_layer(n) for n in sorted({r["n"] for r in reqs})}
     fields = {n: (np.ascontiguousarray(rho.reshape(-1)), np.ascontiguousarray(u.reshape(2, -1)))
@@ -47,7 +48,7 @@ def run_stream(reqs, *, pool_bytes: Optional[int] = None, max_active: int = 64,
     lag = np.zeros(len(reqs))
     ids = []
     with elbm.Server(pool_bytes, max_active=max_active, round_steps=round_steps,
-                     device=dev, stream=stream) as srv:
+                     preempt_rounds=preempt_rounds, device=dev, stream=stream) as srv:
         t0 = time.perf_counter()
         for r in reqs:
             if realtime:
@@ -87,7 +88,8 @@ def run_stream(reqs, *, pool_bytes: Optional[int] = None, max_active: int = 64,
         mlups=updates / span / 1e6 if span > 0 else None, span_s=span,
         site_updates=updates, rounds=st["rounds"], launches=st["launches"],
         max_resident=st["max_resident"], pool_bytes=int(pool_bytes),
-        max_active=max_active, round_steps=round_steps,
+        max_active=max_active, round_steps=round_steps, preempt_rounds=preempt_rounds,
+        preemptions=st["preemptions"],
         latency_s=lat.tolist(), outputs=outs)
 
 

@@ -214,6 +214,11 @@ def test_server_argument_errors_before_device_work():
     assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
     sc = elbm.ServerConfig(C.c_void_p(4096), 1 << 20, None, 4, 0)
     assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    sc = elbm.ServerConfig(C.c_void_p(4096), 1 << 20, None, 4, 10, -1, 0)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
+    assert b"preempt_rounds" in L.elbm_last_error()
+    sc = elbm.ServerConfig(C.c_void_p(4096), 1 << 20, None, 4, 10, 0, 1)
+    assert L.elbm_server_create(C.byref(sc), C.byref(h)) == -1
     assert L.elbm_server_create(None, C.byref(h)) == -1
     assert L.elbm_server_submit(None, None, None) == -1
     assert L.elbm_server_poll(None, 1, None) == -1

@@ -214,3 +214,89 @@ def test_serving_stream_small(gpu):
         torch.cuda.synchronize()
         assert torch.equal(res["outputs"][k][0], r0)
         assert torch.equal(res["outputs"][k][1], u0)
+
+
+LONG = (2, (128, 128, 1), 20000, dict(storage="f16dev", beta=0.99))
+SHORT = [(2, (64, 64, 1), 60, dict(storage="f32", beta=0.99)),
+         (3, (16, 12, 9), 40, dict(storage="f32dev", beta=0.98)),
+         (19, (14, 10, 9), 60, dict(storage="f32", beta=0.98))]
+# for a pool with room for LONG only: each needs more than LONG's state leaves
+SHORT_POOL = [(2, (96, 96, 1), 60, dict(storage="f32", beta=0.99)),
+              (3, (16, 12, 9), 40, dict(storage="f32dev", beta=0.98)),
+              (2, (80, 96, 1), 60, dict(storage="f32", beta=0.99))]
+
+
+def _footprint(gpu, D, shape, kw):
+    lat = {1: "d1q3", 2: "d2q9", 3: "d3q27", 19: "d3q19"}[D]
+    cfg = gpu.make_config(lat, *shape, **kw)
+    N = int(np.prod(shape))
+    up = lambda b: (b + 255) // 256 * 256
+    return up(gpu.state_bytes(cfg)) + up(N * (1 + _dim(D)) * 8)
+
+
+def _run_long_then_short(gpu, pool, max_active, preempt_rounds, short=SHORT):
+    """Submit LONG, wait until it runs, then the short requests; return the
+    requests, fields, outputs, request infos (LONG first) and server stats."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.Stream()
+    reqs = [LONG] + short
+    fields = [_fields(D, shp, 300 + k) for k, (D, shp, _, _) in enumerate(reqs)]
+    outs, ids = [], []
+    with gpu.Server(pool, max_active=max_active, round_steps=20, preempt_rounds=preempt_rounds,
+                    stream=stream) as srv:
+        for k, ((D, shp, steps, kw), (rho, u)) in enumerate(zip(reqs, fields)):
+            N = int(np.prod(shp))
+            with torch.cuda.stream(stream):
+                o = (torch.empty(N, dtype=torch.float64, device=dev),
+                     torch.empty(_dim(D), N, dtype=torch.float64, device=dev))
+            outs.append(o)
+            ids.append(srv.submit(D, *shp, rho0=rho, u0=u, nsteps=steps, out_rho=o[0],
+                                  out_u=o[1], **kw))
+            if k == 0:
+                t0 = time.time()
+                while srv.poll(ids[0])["state"] != "running" and time.time() - t0 < 10:
+                    time.sleep(0.0005)
+                assert srv.poll(ids[0])["state"] == "running"
+        for i in ids:
+            srv.wait(i, 120.0)
+        infos = [srv.poll(i) for i in ids]
+        st = srv.stats()
+    torch.cuda.synchronize()
+    return reqs, fields, outs, infos, st
+
+
+@pytest.mark.parametrize("limit", ["slots", "pool"])
+def test_server_preemption_is_exact_and_lets_short_requests_through(gpu, limit):
+    """With preemption, a long request resident when short ones arrive is
+    moved out to host memory (its checkpoint) and resumed later: the short
+    requests finish first, and every result, the preempted one included,
+    equals its run alone bitwise.  The head of the queue is blocked either by
+    the slot limit (one slot) or by the pool (room for one request)."""
+    if limit == "slots":
+        pool, slots, short = 64 << 20, 1, SHORT
+    else:
+        D, shp, _, kw = LONG
+        lat = {2: "d2q9"}[D]
+        pool = _footprint(gpu, D, shp, kw) + 4096
+        left = pool - (gpu.state_bytes(gpu.make_config(lat, *shp, **kw)) + 255) // 256 * 256
+        slots, short = 8, SHORT_POOL
+        assert all(_footprint(gpu, d, sh, k) > left for d, sh, _, k in short)
+        assert all(_footprint(gpu, d, sh, k) <= pool for d, sh, _, k in short)
+    reqs, fields, outs, infos, st = _run_long_then_short(gpu, pool, slots, preempt_rounds=2,
+                                                         short=short)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["preemptions"] >= 1 and infos[0]["preemptions"] >= 1
+    assert all(inf["t_done"] < infos[0]["t_done"] for inf in infos[1:])
+    for k, ((D, shp, steps, kw), (rho, u), inf) in enumerate(zip(reqs, fields, infos)):
+        assert inf["state"] == "done" and inf["steps_done"] == steps
+        r0, u0, _ = _alone(gpu, D, shp, rho, u, steps, **kw)
+        assert np.array_equal(outs[k][0].cpu().numpy(), r0), k
+        assert np.array_equal(outs[k][1].cpu().numpy(), u0), k
+
+
+def test_server_without_preemption_keeps_arrival_order(gpu):
+    """preempt_rounds = 0: the long request keeps its slot to the end."""
+    reqs, fields, outs, infos, st = _run_long_then_short(gpu, 64 << 20, 1, preempt_rounds=0)
+    assert st["completed"] == len(reqs) and st["preemptions"] == 0
+    assert all(inf["t_done"] > infos[0]["t_done"] for inf in infos[1:])
+    assert all(inf["preemptions"] == 0 for inf in infos)
