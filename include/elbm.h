@@ -341,7 +341,9 @@ typedef struct {
   int64_t preemptions;  /* requests moved out to host memory (preempt_rounds) */
 } elbm_server_stats;
 
-/* Create a server; starts its scheduler thread on the current device. */
+/* Create a server; starts its scheduler thread on the current device.
+ * ELBM_EINVAL for a NULL or misaligned pool, max_active or round_steps < 1,
+ * preempt_rounds < 0 or reserved != 0. */
 elbm_status elbm_server_create(const elbm_server_config *cfg, elbm_server **out);
 
 /* Queue a request (thread-safe, returns at once).  The configuration and the
