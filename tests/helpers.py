@@ -306,3 +306,25 @@ def mp_root_burg(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
             else:
                 lo = mid
         return lo
+
+
+def check_collision_invariants(orc, lat, f0, f1, ag, W, rng_seed):
+    """Per-site invariants of one collision f0 -> f1 at alpha = ag (FP64,
+    recomputed on the CPU): positive populations; mass and momentum to
+    1e-14 rho; the discrete H-theorem H(f1) <= H(f0) up to 8 eps rho
+    max(1, sum_i (f_i / rho) |ln(f_i / W_i)|) of rounding; and, where ag is
+    given, Eq. (7) G(ag) = H(f*(ag)) - H(f0) <= 1e-14 rho on 200 sampled
+    sites, G evaluated by the oracle."""
+    assert np.all(f1 > 0)
+    c, _ = orc.lattice(lat)
+    rho = f0.sum(0)
+    assert np.all(np.abs(f1.sum(0) - rho) <= 1e-14 * rho)
+    for a in range(c.shape[1]):
+        assert np.all(np.abs(c[:, a] @ f1 - c[:, a] @ f0) <= 1e-14 * rho)
+    if ag is not None:
+        N = f0.shape[1]
+        for s in np.random.default_rng(rng_seed).choice(N, min(N, 200), replace=False):
+            assert orc.G(lat, f0[:, s], ag[s]) <= 1e-14 * rho[s]
+    Hs = lambda f: (f * np.log(f / W)).sum(0)
+    tau = 8 * 2.0 ** -52 * rho * np.maximum(1.0, (f0 / rho * np.abs(np.log(f0 / W))).sum(0))
+    assert np.all(Hs(f1) - Hs(f0) <= tau)

@@ -131,6 +131,23 @@ def test_q19_one_step_storages(gpu, orc, shape, storage, mode):
     sim.close()
 
 
+@pytest.mark.parametrize("eps,log_uniform", [(0.05, True), (0.7, False)])
+@pytest.mark.parametrize("mode", ["closed", "secant", "newton"])
+def test_q19_per_site_invariants(gpu, orc, eps, log_uniform, mode):
+    """One collision on the kernel's own output (FP64 storage, f~ read back
+    where the step wrote it), recomputed on the CPU: positivity, mass and
+    momentum to 1e-14 rho, the per-site H-theorem up to rounding, and Eq. (7)
+    at the kernel's alpha for the solvers that bound the root from below."""
+    N = int(np.prod(RAGGED))
+    f0 = _state(N, seed=1990 + len(mode), eps=eps, log_uniform=log_uniform)
+    sim = _sim(gpu, RAGGED, f0, storage="f64", beta=0.98, mode=mode, diag=gpu.DIAG_ALPHA)
+    sim.step(1)
+    f1 = sim.gather(np.arange(N), 1).cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    sim.close()
+    H.check_collision_invariants(orc, 19, f0, f1, None if mode == "newton" else ag, W19, 19)
+
+
 def test_q19_rare_tier_states(gpu, orc):
     """States far from equilibrium (alpha_* < 2 on many sites): the deferred
     rare path (long series, log1p forms) against the oracle, FP64."""
