@@ -302,7 +302,8 @@ typedef struct {
                            memory (a checkpoint, see elbm_export), their pool
                            block is freed and they re-enter the queue at the
                            back; re-admitted, they continue from the
-                           checkpoint bit for bit                            */
+                           checkpoint bit for bit.  A victim for which no
+                           pinned host memory can be had stays resident  */
   int32_t reserved;     /* must be 0                                         */
 } elbm_server_config;
 

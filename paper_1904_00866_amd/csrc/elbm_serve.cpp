@@ -483,11 +483,18 @@ void preempt(elbm_server* s, std::unique_lock<std::mutex>& lk) {
         buf[k].bytes = n;
       }
     }
-    if (buf[k].p) st[k] = elbm::checkpoint_to_host(cand[k]->sim, buf[k].p, n, &tk[k]);
+    st[k] = buf[k].p ? elbm::checkpoint_to_host(cand[k]->sim, buf[k].p, n, &tk[k]) : ELBM_ENOMEM;
   }
   lk.lock();
   for (size_t k = 0; k < nv; ++k) {
     Req* r = cand[k];
+    if (st[k] == ELBM_ENOMEM) {
+      // no host memory for the checkpoint: nothing was enqueued, the victim
+      // stays resident and the head waits as without preemption
+      recycle_pinned(s, buf[k]);
+      s->active.push_back(r);
+      continue;
+    }
     if (st[k] != ELBM_OK) {
       // the server stops here: the victim is failed with the residents
       mark_broken(s, std::string("preemption: ") + elbm_last_error());
