@@ -367,6 +367,35 @@ def test_per_site_h_theorem_on_the_gpu(gpu, orc, D, eps, log_uniform, mode):
 
 
 @pytest.mark.parametrize("D", [2, 3])
+def test_collision_invariants_along_a_run(gpu, orc, D):
+    """The per-site invariants at sampled steps of a flow (2-D shear layer
+    128^2 at nu = 1e-5; 3-D Taylor-Green 32^3 at Re = 1600), FP64 storage,
+    closed form: the pre-collision f(., t) is read, one step taken, and the
+    f~(., t) it wrote checked against f(., t) on the CPU."""
+    if D == 2:
+        n, shape = 128, (128, 128, 1)
+        rho, u = Wk.shear_layer(n)
+        beta = Wk.beta_from_nu(1e-5)
+    else:
+        n, shape = 32, (32, 32, 32)
+        rho, u = Wk.taylor_green_3d(n)
+        beta = Wk.tgv3d_beta(n)
+    W = H.textbook_weights(D)[:, None]
+    N = int(np.prod(shape))
+    sim = _sim(gpu, D, shape, rho=rho, u=u, storage="f64", beta=beta, diag=gpu.DIAG_ALPHA)
+    t = 0
+    for t_check in (0, 40, 300):
+        sim.step(t_check - t)
+        f = sim.populations().cpu().numpy()
+        sim.step(1)
+        t = t_check + 1
+        f1 = sim.gather(np.arange(N), 1).cpu().numpy()
+        ag = sim.alpha_field().cpu().numpy()
+        H.check_collision_invariants(orc, D, f, f1, ag, W, t_check)
+    sim.close()
+
+
+@pytest.mark.parametrize("D", [2, 3])
 def test_secant_iterates_on_the_gpu(gpu, D):
     """The modified secant on the kernel: its first iterate from alpha = 1
     is Eq. (9) (G(1) = -D exactly), so one iteration reproduces the closed
