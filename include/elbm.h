@@ -142,7 +142,9 @@ enum {
 
 typedef struct {
   int32_t lattice;       /* ELBM_D1Q3 / ELBM_D2Q9 / ELBM_D3Q27 / ELBM_D3Q19 */
-  int32_t nx, ny, nz;    /* box, each >= 1                                */
+  int32_t nx, ny, nz;    /* box, each in [1, 2^20 - 1]; nz = 1 for D2Q9,
+                            ny = nz = 1 for D1Q3; N = nx ny nz at most
+                            2^31 - 1 sites (32-bit site indices)        */
   double beta;           /* Eq. (2), 0 < beta < 1                         */
   int32_t alpha_mode;    /* ELBM_ALPHA_*                                  */
   int32_t storage;       /* ELBM_STORE_*                                  */
