@@ -367,6 +367,42 @@ def test_per_site_h_theorem_on_the_gpu(gpu, orc, D, eps, log_uniform, mode):
 
 
 @pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
+def test_collision_invariants_reduced_storage(gpu, orc, D, storage):
+    """With FP64 site arithmetic the only loss of a collision in a reduced
+    storage format is the one rounding of each stored output: per site,
+    mass and momentum move by at most the sum of those roundings, H rises
+    by at most sum_i |ln(f~_i / W_i) + 1| times them (plus the FP64
+    rounding bound), and every population stays positive.  Checked on the
+    decoded pre-collision state and the decoded f~ the step wrote."""
+    shape = SHAPES[D]
+    N = int(np.prod(shape))
+    W = H.textbook_weights(D)[:, None]
+    f0 = Wk.random_populations(H.textbook_weights(D), N, 0.3, 4500 + D + len(storage), tilt=0.1)
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.98)
+    fq = sim.populations().cpu().numpy()  # decoded stored state
+    sim.step(1)
+    f1 = sim.gather(np.arange(N), 1).cpu().numpy()
+    sim.close()
+    if storage == "f32":
+        r = 2.0 ** -24 * np.abs(f1) * 1.01
+    elif storage == "f32dev":
+        r = W * (2.0 ** -24 * np.abs(f1 / W - 1.0) * 1.01 + 1e-12)
+    else:
+        r = W * (2.0 ** -11 * np.abs(f1 / W - 1.0) * 1.01 + 2.0 ** -24)
+    assert np.all(f1 > 0)
+    rho = fq.sum(0)
+    bound = r.sum(0) + 1e-14 * rho
+    assert np.all(np.abs(f1.sum(0) - rho) <= bound)
+    c, _ = orc.lattice(D)
+    for a in range(D):
+        assert np.all(np.abs(c[:, a] @ f1 - c[:, a] @ fq) <= bound)
+    Hs = lambda f: (f * np.log(f / W)).sum(0)
+    tau = 8 * 2.0 ** -52 * rho * np.maximum(1.0, (fq / rho * np.abs(np.log(fq / W))).sum(0))
+    assert np.all(Hs(f1) - Hs(fq) <= tau + (np.abs(np.log(f1 / W) + 1.0) * r).sum(0))
+
+
+@pytest.mark.parametrize("D", [2, 3])
 def test_collision_invariants_along_a_run(gpu, orc, D):
     """The per-site invariants at sampled steps of a flow (2-D shear layer
     128^2 at nu = 1e-5; 3-D Taylor-Green 32^3 at Re = 1600), FP64 storage,
