@@ -323,7 +323,7 @@ typedef struct {
 } elbm_request;
 
 enum { ELBM_REQ_QUEUED = 0, ELBM_REQ_RUNNING = 1, ELBM_REQ_DONE = 2,
-       ELBM_REQ_FAILED = 3 };
+       ELBM_REQ_FAILED = 3, ELBM_REQ_CANCELLED = 4 };
 
 typedef struct {
   int32_t state;        /* ELBM_REQ_* (a preempted request is QUEUED)        */
@@ -342,6 +342,7 @@ typedef struct {
   int64_t max_resident; /* most simulations resident at once                 */
   double t_first_submit, t_last_done;
   int64_t preemptions;  /* requests moved out to host memory (preempt_rounds) */
+  int64_t cancelled;    /* requests ended by elbm_server_cancel              */
 } elbm_server_stats;
 
 /* Create a server; starts its scheduler thread on the current device.
@@ -358,10 +359,18 @@ elbm_status elbm_server_submit(elbm_server *srv, const elbm_request *req,
 /* State and times of a request (HOST info). */
 elbm_status elbm_server_poll(elbm_server *srv, int64_t id, elbm_request_info *info);
 
-/* Block until request id is done or failed, or timeout_s seconds pass
- * (ELBM_ESTATE on timeout; timeout_s < 0 waits without limit; ELBM_EDEVICE
- * if the request failed).  Done means its final rho/u are in out_rho/out_u. */
+/* Block until request id is done, failed or cancelled, or timeout_s seconds
+ * pass (ELBM_ESTATE on timeout or cancellation; timeout_s < 0 waits without
+ * limit; ELBM_EDEVICE if the request failed).  Done means its final rho/u
+ * are in out_rho/out_u. */
 elbm_status elbm_server_wait(elbm_server *srv, int64_t id, double timeout_s);
+
+/* Cancel a queued or running request (thread-safe, returns at once).  The
+ * scheduler ends it between rounds as ELBM_REQ_CANCELLED and frees its pool
+ * block and host copies; out_rho/out_u are not written.  A request whose
+ * last round is already enqueued completes as ELBM_REQ_DONE instead.
+ * ELBM_EINVAL for an unknown id, ELBM_ESTATE if it has already finished. */
+elbm_status elbm_server_cancel(elbm_server *srv, int64_t id);
 
 /* The simulation of a completed keep_state request (valid until release). */
 elbm_status elbm_server_sim(elbm_server *srv, int64_t id, elbm_sim **sim);

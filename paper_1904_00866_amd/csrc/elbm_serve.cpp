@@ -131,6 +131,7 @@ struct Req {
   Pinned ckpt;               // populations while preempted, until resumed
   size_t ckpt_bytes = 0;
   int64_t ckpt_t = 0;
+  bool cancel = false;       // elbm_server_cancel, applied between rounds
 };
 
 // Work enqueued on the stream, and what to do once the GPU has passed it.
@@ -164,7 +165,8 @@ struct elbm_server {
   bool stop = false;
   bool broken = false;
   std::string error;
-  uint64_t kick = 0;  // bumped by submit, release and destroy
+  uint64_t kick = 0;  // bumped by submit, release, cancel and destroy
+  bool cancels = false;  // some request carries a cancel flag
   int64_t next_id = 1;
   elbm_server_stats stats{};
   double t0 = 0;
@@ -516,6 +518,52 @@ void preempt(elbm_server* s, std::unique_lock<std::mutex>& lk) {
   }
 }
 
+// Cancellations (elbm_server_cancel), applied by the scheduler thread
+// between rounds with the lock held, so that no launch is being enqueued for
+// the simulations it releases.  A queued request drops its host copies; its
+// checkpoint, if it was preempted, may still be the destination of the copy
+// that preempted it, so it is recycled only once the stream has passed the
+// next round.  A resident request gives back its simulation and pool block
+// at once: every later use of the block is enqueued behind its last step on
+// the same stream.  A request whose last round is already enqueued is no
+// longer resident and completes.
+void apply_cancels(elbm_server* s) {
+  if (!s->cancels) return;
+  s->cancels = false;
+  const double t = now_s() - s->t0;
+  auto cancelled = [&](Req* r) {
+    r->state = ELBM_REQ_CANCELLED;
+    r->t_done = t;
+    s->stats.cancelled++;
+  };
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    Req* r = *it;
+    if (!r->cancel) {
+      ++it;
+      continue;
+    }
+    recycle_pinned(s, r->host);
+    r->host = Pinned{};
+    if (r->ckpt.p) s->pending.pinned.push_back(r->ckpt);
+    r->ckpt = Pinned{};
+    cancelled(r);
+    it = s->queue.erase(it);
+  }
+  std::vector<Req*> still;
+  for (Req* r : s->active) {
+    if (!r->cancel) {
+      still.push_back(r);
+      continue;
+    }
+    elbm::release_sim(r->sim);
+    r->sim = nullptr;
+    s->pool->release(r->off, r->state_bytes);
+    cancelled(r);
+  }
+  s->active.swap(still);
+  s->cv.notify_all();
+}
+
 void worker_main(elbm_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
@@ -551,6 +599,7 @@ void worker_main(elbm_server* s) {
       seen = s->kick;
       continue;
     }
+    apply_cancels(s);
     preempt(s, lk);
     if (s->broken) continue;
     admit(s, lk);
@@ -704,14 +753,32 @@ elbm_status elbm_server_wait(elbm_server* s, int64_t id, double timeout_s) {
   std::unique_lock<std::mutex> lk(s->mu);
   const Req* r = find_req(s, id);
   if (!r) return set_error(ELBM_EINVAL, "unknown request id");
-  auto done = [r] { return r->state == ELBM_REQ_DONE || r->state == ELBM_REQ_FAILED; };
+  auto done = [r] {
+    return r->state == ELBM_REQ_DONE || r->state == ELBM_REQ_FAILED ||
+           r->state == ELBM_REQ_CANCELLED;
+  };
   if (timeout_s < 0) {
     s->cv.wait(lk, done);
   } else if (!s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
     return set_error(ELBM_ESTATE, "timed out waiting for the request");
   }
   if (r->state == ELBM_REQ_DONE) return ELBM_OK;
+  if (r->state == ELBM_REQ_CANCELLED) return set_error(ELBM_ESTATE, "request was cancelled");
   return set_error(ELBM_EDEVICE, s->error.empty() ? "request failed" : s->error.c_str());
+}
+
+elbm_status elbm_server_cancel(elbm_server* s, int64_t id) {
+  if (!s) return set_error(ELBM_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  Req* r = find_req(s, id);
+  if (!r) return set_error(ELBM_EINVAL, "unknown request id");
+  if (r->state != ELBM_REQ_QUEUED && r->state != ELBM_REQ_RUNNING)
+    return set_error(ELBM_ESTATE, "request already finished");
+  r->cancel = true;
+  s->cancels = true;
+  s->kick++;
+  s->cv.notify_all();
+  return ELBM_OK;
 }
 
 elbm_status elbm_server_sim(elbm_server* s, int64_t id, elbm_sim** sim) {

@@ -36,9 +36,10 @@ EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_pop
            "elbm_alpha_field", "elbm_stats", "elbm_time", "elbm_destroy",
            "elbm_last_error", "elbm_step_batch", "elbm_server_create", "elbm_server_submit",
            "elbm_server_poll", "elbm_server_wait", "elbm_server_sim", "elbm_server_release",
+           "elbm_server_cancel",
            "elbm_server_get_stats", "elbm_server_destroy", "elbm_checkpoint_bytes",
            "elbm_export", "elbm_import"]
-REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
 class ElbmError(RuntimeError):
@@ -88,7 +89,8 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("rounds", C.c_int64), ("launches", C.c_int64), ("site_updates", C.c_int64),
                 ("max_resident", C.c_int64), ("t_first_submit", C.c_double),
-                ("t_last_done", C.c_double), ("preemptions", C.c_int64)]
+                ("t_last_done", C.c_double), ("preemptions", C.c_int64),
+                ("cancelled", C.c_int64)]
 
 
 _lib = None
@@ -126,6 +128,7 @@ def lib():
         L.elbm_server_wait.argtypes = [vp, C.c_int64, C.c_double]
         L.elbm_server_sim.argtypes = [vp, C.c_int64, C.POINTER(vp)]
         L.elbm_server_release.argtypes = [vp, C.c_int64]
+        L.elbm_server_cancel.argtypes = [vp, C.c_int64]
         L.elbm_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.elbm_server_destroy.argtypes = [vp]
         L.elbm_checkpoint_bytes.argtypes = [vp]
@@ -364,6 +367,9 @@ class Server:
 
     def wait(self, rid: int, timeout: float = -1.0):
         _check(lib().elbm_server_wait(self.handle, int(rid), float(timeout)))
+
+    def cancel(self, rid: int):
+        _check(lib().elbm_server_cancel(self.handle, int(rid)))
 
     def simulation(self, rid: int) -> KeptSimulation:
         h = C.c_void_p()

@@ -224,4 +224,5 @@ def test_server_argument_errors_before_device_work():
     assert L.elbm_server_poll(None, 1, None) == -1
     assert L.elbm_server_wait(None, 1, 0.0) == -1
     assert L.elbm_server_release(None, 1) == -1
+    assert L.elbm_server_cancel(None, 1) == -1
     assert L.elbm_server_destroy(None) == 0

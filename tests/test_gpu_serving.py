@@ -300,3 +300,55 @@ def test_server_without_preemption_keeps_arrival_order(gpu):
     assert st["completed"] == len(reqs) and st["preemptions"] == 0
     assert all(inf["t_done"] > infos[0]["t_done"] for inf in infos[1:])
     assert all(inf["preemptions"] == 0 for inf in infos)
+
+
+def test_server_cancel(gpu):
+    """Cancellation: with a pool that holds the long request only, a queued
+    request is dropped without running and the running long request ends
+    between rounds, freeing its block for the request waiting behind it,
+    which then completes with the same result as alone.  Neither cancelled
+    request writes its outputs; a finished request cannot be cancelled."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.Stream()
+    D, shp, _, kw = LONG
+    pool = _footprint(gpu, D, shp, kw) + 4096
+    reqs = [LONG, SHORT_POOL[0], SHORT_POOL[2]]
+    fields = [_fields(d, sh, 500 + k) for k, (d, sh, _, _) in enumerate(reqs)]
+    outs, ids = [], []
+    with gpu.Server(pool, max_active=8, round_steps=20, stream=stream) as srv:
+        for k, ((d, sh, steps, kw_), (rho, u)) in enumerate(zip(reqs, fields)):
+            N = int(np.prod(sh))
+            with torch.cuda.stream(stream):
+                o = (torch.full((N,), float("nan"), dtype=torch.float64, device=dev),
+                     torch.full((_dim(d), N), float("nan"), dtype=torch.float64, device=dev))
+            outs.append(o)
+            ids.append(srv.submit(d, *sh, rho0=rho, u0=u, nsteps=steps, out_rho=o[0],
+                                  out_u=o[1], **kw_))
+            if k == 0:
+                t0 = time.time()
+                while srv.poll(ids[0])["state"] != "running" and time.time() - t0 < 10:
+                    time.sleep(0.0005)
+        assert srv.poll(ids[0])["state"] == "running"
+        assert srv.poll(ids[2])["state"] == "queued"
+        srv.cancel(ids[2])
+        srv.cancel(ids[0])
+        for i in (ids[0], ids[2]):
+            with pytest.raises(gpu.ElbmError, match="cancelled"):
+                srv.wait(i, 60.0)
+        srv.wait(ids[1], 60.0)
+        infos = [srv.poll(i) for i in ids]
+        with pytest.raises(gpu.ElbmError, match="ESTATE"):
+            srv.cancel(ids[1])
+        with pytest.raises(gpu.ElbmError, match="ESTATE"):
+            srv.cancel(ids[0])
+        st = srv.stats()
+    torch.cuda.synchronize()
+    assert [inf["state"] for inf in infos] == ["cancelled", "done", "cancelled"]
+    assert infos[0]["steps_done"] < LONG[2] and infos[2]["t_admit"] == 0
+    assert st["cancelled"] == 2 and st["completed"] == 1 and st["failed"] == 0
+    for k in (0, 2):
+        assert torch.isnan(outs[k][0]).all() and torch.isnan(outs[k][1]).all()
+    d, sh, steps, kw_ = reqs[1]
+    r0, u0, _ = _alone(gpu, d, sh, *fields[1], steps, **kw_)
+    assert np.array_equal(outs[1][0].cpu().numpy(), r0)
+    assert np.array_equal(outs[1][1].cpu().numpy(), u0)
