@@ -532,24 +532,46 @@ static double solve_bisect(const lat_t *L, const double *feq, const double *x,
 
 /* Bracketed Newton iteration for the root of Eq. (4) on [1, alpha_max],
  * started at alpha_* (at the bracket midpoint when alpha_* = alpha_max, where
- * G' is unbounded).  A step leaving the bracket is replaced by bisection.
- * Stops when the step is below 1e-13 alpha: the FP64 rounding of G near its
- * root already moves alpha by about that much, so smaller steps only follow
- * rounding noise until the bracket collapses. */
+ * G' is unbounded).  A step that leaves the bracket is replaced by the
+ * midpoint; the iteration stops at a step (Newton or midpoint) below
+ * 1e-13 alpha: the FP64 rounding of G near its root already moves alpha by
+ * about that much, so smaller steps only follow rounding noise.  A Newton
+ * step below that size that rounds onto (or past) the end of the bracket is
+ * a converged step too, and stops there instead of restarting bisection.
+ *
+ * G is convex with G(1) = -D <= 0 and G' > 0 on (1, alpha_max], so G < 0 on
+ * [1, root) and G > 0 beyond it, and a Newton step from a point with G < 0
+ * lands at or beyond the root.  Whether the root lies inside [1, alpha_max]
+ * (G(alpha_max) > 0) is therefore only asked when a step leaves the bracket
+ * while its upper end is still alpha_max: if G(alpha_max) <= 0 the root lies
+ * beyond and alpha_max is returned.  The result is the root to the rounding
+ * of G; it can sit on either side of it. */
 static double solve_newton(const lat_t *L, const double *feq, const double *x,
                            double amax, double astar, int maxit, int *iters) {
   double lo = 1.0, hi = amax;
-  *iters = 0;
-  if (G_of(L, feq, x, hi) <= 0.0) return hi;
+  int hi_positive = 0; /* G(hi) > 0 known */
   double a = (astar < amax) ? astar : 0.5 * (lo + hi);
+  *iters = 0;
   for (int k = 1; k <= maxit; ++k) {
     double g = G_of(L, feq, x, a);
     *iters = k;
     if (g == 0.0) return a;
-    if (g > 0.0) hi = a;
-    else lo = a;
+    if (g > 0.0) {
+      hi = a;
+      hi_positive = 1;
+    } else {
+      lo = a;
+    }
     double an = a - g / dG_of(L, feq, x, a);
-    if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+    if (!(an > lo && an < hi)) {
+      /* a converged step that rounds onto (or just past) the bracket end */
+      if (fabs(an - a) <= 1e-13 * a) return (an < lo) ? lo : (an > hi) ? hi : an;
+      if (!hi_positive) {
+        if (G_of(L, feq, x, hi) <= 0.0) return hi;
+        hi_positive = 1;
+      }
+      an = 0.5 * (lo + hi);
+    }
     if (fabs(an - a) <= 1e-13 * a) return an;
     a = an;
   }

@@ -265,7 +265,16 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
         if (gv > 0.0) hi = a;
         else lo = a;
         double an = a - gv / dS;
-        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+        if (!(an > lo && an < hi)) {
+          // a converged step that rounds onto the end of the bracket stops
+          // there; a longer one is replaced by the midpoint (G(alpha_max) is
+          // infinite, so the root always lies inside)
+          if (fabs(an - a) <= 1e-13 * a) {
+            a = fmin(fmax(an, lo), hi);
+            break;
+          }
+          an = 0.5 * (lo + hi);
+        }
         if (fabs(an - a) <= 1e-13 * a) {
           a = an;
           break;

@@ -742,32 +742,57 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
         if (alpha < R(0)) alpha = lo;
       }
     } else if constexpr (MODE == kNewton) {
-      // Eq. (4) by Newton from alpha_* inside the bracket [1, alpha_max].
-      if (S_log(v, amax) - Dv <= R(0)) {
-        alpha = amax;
-      } else {
-        R lo = R(1), hi = amax;
-        R a = (astar < amax) ? astar : R(0.5) * (lo + hi);
-        for (int k = 1; k <= d.root_max_iter; ++k) {
-          R Sv, dS;
-          S_dS_log(v, a, Sv, dS);
-          const R gv = Sv - Dv;
-          iters = k;
-          if (gv == R(0)) break;
-          if (gv > R(0)) hi = a;
-          else lo = a;
-          R an = a - gv / dS;
-          if (!(an > lo && an < hi)) an = R(0.5) * (lo + hi);
-          // stop at a step below 1e-13 alpha (rounding of G near the root
-          // moves alpha by about that much)
+      // Eq. (4) by Newton from alpha_* inside the bracket [1, alpha_max]
+      // (from its midpoint when alpha_* = alpha_max, where G' is unbounded).
+      // G is convex, G(1) <= 0 and G' > 0 beyond 1, so a step from a point
+      // with G < 0 lands at or beyond the root; whether the root lies inside
+      // the bracket (G(alpha_max) > 0) is asked only when a step leaves it
+      // while its upper end is still alpha_max.  A step leaving the bracket
+      // is replaced by the midpoint; the iteration stops at a step below
+      // 1e-13 alpha (the rounding of G near the root moves alpha by about
+      // that much), and a converged Newton step that rounds onto the end of
+      // the bracket stops there.
+      R lo = R(1), hi = amax;
+      bool hi_pos = false;  // G(hi) > 0 known
+      R a = (astar < amax) ? astar : R(0.5) * (lo + hi);
+      alpha = R(-1);
+      for (int k = 1; k <= d.root_max_iter; ++k) {
+        R Sv, dS;
+        S_dS_log(v, a, Sv, dS);
+        const R gv = Sv - Dv;
+        iters = k;
+        if (gv == R(0)) {
+          alpha = a;
+          break;
+        }
+        if (gv > R(0)) {
+          hi = a;
+          hi_pos = true;
+        } else {
+          lo = a;
+        }
+        R an = a - gv / dS;
+        if (!(an > lo && an < hi)) {
           if (fabs(an - a) <= R(1e-13) * a) {
-            a = an;
+            alpha = fmin(fmax(an, lo), hi);
             break;
           }
-          a = an;
+          if (!hi_pos) {
+            if (S_log(v, hi) - Dv <= R(0)) {
+              alpha = hi;
+              break;
+            }
+            hi_pos = true;
+          }
+          an = R(0.5) * (lo + hi);
         }
-        alpha = a;
+        if (fabs(an - a) <= R(1e-13) * a) {
+          alpha = an;
+          break;
+        }
+        a = an;
       }
+      if (alpha < R(0)) alpha = a;
     }
   }
   o.alpha = alpha;

@@ -137,11 +137,13 @@ def mp_G(D: int, f, alpha, dps: int = 50) -> mp.mpf:
         return mp_H(fs, W) - mp_H(fm, W)
 
 
-def mp_alpha_closed(D: int, f, dps: int = 60) -> mp.mpf:
+def mp_alpha_closed(D: int, f, dps: int = 60, full: bool = False):
     """The closed-form alpha in mpmath: alpha_* = min(2, alpha_max)
     (Eq. (8), alpha_max = 1 + 1 / max_i x_i over x_i > 0), accepted when
     H(f*(alpha_*)) <= H(f), else Eq. (9) clipped to [1, alpha_*]; the
-    equilibrium from the multiplier minimisation, f taken exactly as given."""
+    equilibrium from the multiplier minimisation, f taken exactly as given.
+    full=True returns (alpha_*, alpha, H(f*(alpha_*)) - H(f),
+    H(f*(alpha_*)) - H(f^eq)), each entropy from Eq. (3) literally."""
     with mp.workdps(dps):
         fm = [mp.mpf(float(v)) for v in f]
         rho = sum(fm)
@@ -152,11 +154,17 @@ def mp_alpha_closed(D: int, f, dps: int = 60) -> mp.mpf:
         xmax = max(fm[i] / feq[i] - 1 for i in range(len(fm)))
         astar = mp.mpf(2) if xmax <= 1 else 1 + 1 / xmax
         fs = [fm[i] + astar * (feq[i] - fm[i]) for i in range(len(fm))]
+        # at alpha_* = alpha_max one component of f*(alpha_*) is zero, up to
+        # the working precision's rounding: read it as zero
+        floor = -mp.mpf(10) ** (-dps + 10) * max(fm)
+        fs = [max(v, mp.mpf(0)) if v > floor else v for v in fs]
         Hs, H0, He = mp_H(fs, W), mp_H(fm, W), mp_H(feq, W)
         Gs, Ds = Hs - H0, Hs - He
         if Gs <= 0:
-            return astar
-        return min(max(astar + Gs / Ds * (1 - astar), mp.mpf(1)), astar)
+            alpha = astar
+        else:
+            alpha = min(max(astar + Gs / Ds * (1 - astar), mp.mpf(1)), astar)
+        return (astar, alpha, Gs, Ds) if full else alpha
 
 
 def mp_root(D: int, f, lo, hi, dps: int = 40, iters: int = 80):
@@ -328,3 +336,12 @@ def check_collision_invariants(orc, lat, f0, f1, ag, W, rng_seed):
     Hs = lambda f: (f * np.log(f / W)).sum(0)
     tau = 8 * 2.0 ** -52 * rho * np.maximum(1.0, (f0 / rho * np.abs(np.log(f0 / W))).sum(0))
     assert np.all(Hs(f1) - Hs(f0) <= tau)
+
+
+def entropy_scale(f, W) -> float:
+    """sum_x sum_i |f_i ln(f_i / W_i)|: the size of the terms whose sum is
+    sum_x H(f(x)) (Eq. (3) summed as in Eq. (6)); that sum cancels between
+    sites with rho above and below 1, so its rounding is relative to this
+    scale, not to the sum itself."""
+    W = np.asarray(W, dtype=np.float64).reshape(-1, 1)
+    return float(np.sum(np.abs(f * np.log(f / W))))

@@ -363,6 +363,66 @@ def test_closed_form_guarantee_against_mpmath(orc):
     assert n_checked >= 30
 
 
+def _far_states(n, D, seed):
+    """Positive states with alpha_max < 2 (some f_i > 2 f_i^eq)."""
+    rng = np.random.default_rng(seed)
+    W = H.textbook_weights(D)
+    out = []
+    while len(out) < n:
+        f = 3.0 * W * (rng.random(len(W)) ** 3 + 1e-3)
+        if H.mp_alpha_closed(D, f, dps=30, full=True)[0] < 2:
+            out.append(f)
+    return out
+
+
+def _phi(y):
+    """(1 + y) ln(1 + y) - y, with the 0 ln 0 = 0 limit at y = -1."""
+    y = np.asarray(y, dtype=np.float64)
+    yy = np.where(y <= -1.0, 0.0, y)
+    return np.where(y <= -1.0, 1.0, (1.0 + yy) * np.log1p(yy) - yy)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_closed_form_value_against_mpmath(orc, D):
+    """The value of Eq. (8) and Eq. (9) against a 60-digit evaluation from
+    the literal entropies of Eq. (3) and the exact constrained minimiser:
+    150 near-equilibrium states (deviation size log-uniform in 3e-5 .. 0.3,
+    half of them moment-preserving) and 20 states with alpha_* = alpha_max < 2.
+
+    Tolerance: the FP64 conditioning of Eq. (9).  With
+    alpha = alpha_* - (alpha_* - 1) G_* / D_*, an absolute error dG in
+    G_* = H(f*(alpha_*)) - H(f) and dD in D_* = H(f*(alpha_*)) - H(f^eq)
+    moves alpha by at most (alpha_* - 1)(|dG| + |dD|) / D_* (G_* <= D_*).
+    Each relative-entropy term f^eq_i phi(y_i) with y = x or (1 - alpha_*) x
+    carries a rounding of a few eps f^eq_i |y_i| (phi(y) ~ y^2/2 formed from
+    O(y) parts), so the bound is
+        |alpha - alpha_mp| <= 4e-16 + 4 eps (alpha_* - 1) S / D_*,
+        S = sum_i f^eq_i (|x_i| + |(1 - alpha_*) x_i|).
+    The oracle reaches 0.70 of the bound without its factor 4.  A wrong
+    denominator (H(f) - H(f^eq) in place of D_*) shifts alpha by about
+    (alpha_* - alpha)^2: 1e-9 at deviations of 1e-4, far outside it."""
+    cfg = orc.Config(D=D, nx=1, beta=0.9, mode="closed")
+    eps = 2.0 ** -52
+    near = _states(150, D, 900 + D)
+    far = _far_states(20, D, 77 + D)
+    n_far = n_eq9 = 0
+    for f in near + far:
+        r = orc.alpha_site(cfg, f)
+        ast_mp, a_mp, gs_mp, _ = H.mp_alpha_closed(D, f, dps=60, full=True)
+        # Eq. (8): alpha_* = min(2, alpha_max), to rounding
+        assert abs(r["alpha_star"] - float(ast_mp)) <= 4 * eps * float(ast_mp), (r, ast_mp)
+        ast = r["alpha_star"]
+        feq = orc.equilibrium(D, r["rho"], r["u"])
+        x = (f - feq) / feq
+        S = float(np.sum(feq * (np.abs(x) + np.abs((1.0 - ast) * x))))
+        Dst = float(np.sum(feq * _phi((1.0 - ast) * x)))
+        tol = 4e-16 + 4 * eps * (ast - 1.0) * S / Dst
+        assert abs(r["alpha"] - float(a_mp)) <= tol, (r["alpha"], float(a_mp), tol, r)
+        n_far += ast < 2.0
+        n_eq9 += gs_mp > 0
+    assert n_far >= 20 and n_eq9 >= 60
+
+
 def test_alpha_tends_to_2_near_equilibrium(orc):
     """For f = f^eq (1 + eps xi): 2 - alpha = O(eps), with the leading term
     (2/3) sum f^eq x^3 / sum f^eq x^2 from phi's Maclaurin series."""
@@ -445,6 +505,34 @@ def test_newton_and_bisection_find_the_nontrivial_root(orc):
         if checked >= 25:
             break
     assert checked >= 20
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_newton_result_side_of_the_root(orc, D):
+    """Where Eq. (4) has to be solved, G is convex with G(1) < 0 and Newton
+    approaches the root from the side G > 0, so it stops at an iterate that
+    can lie on either side of the root by the FP64 noise of G: the result
+    satisfies Eq. (7) only to rounding, |G(alpha)| <= 8 eps S in 40-digit
+    arithmetic (S = sum_i f^eq_i (|x_i| + |(1 - alpha) x_i|), the scale of
+    the rounding of the relative-entropy terms), unlike Eq. (9) and
+    bisection, which keep G <= 0.  Both signs occur."""
+    cn = orc.Config(D=D, nx=1, beta=0.9, mode="newton", root_max_iter=60)
+    eps = 2.0 ** -52
+    n, signs = 0, set()
+    for f in _states(40, D, 31 + D) + _far_states(8, D, 5 + D):
+        r = orc.alpha_site(cn, f)
+        if r["guard"] or r["alpha"] == r["alpha_max"]:
+            continue  # no root inside [1, alpha_max]: alpha_max is returned
+        n += 1
+        assert r["iters"] <= 12
+        a = r["alpha"]
+        feq = orc.equilibrium(D, r["rho"], r["u"])
+        x = (f - feq) / feq
+        S = float(np.sum(feq * (np.abs(x) + np.abs((1.0 - a) * x))))
+        g = float(H.mp_G(D, f, a, dps=40))
+        assert abs(g) <= 8 * eps * S + 1e-17 * r["rho"], (g, S, r)
+        signs.add(g > 0)
+    assert n >= 30 and signs == {True, False}
 
 
 def test_newton_root_exceeds_closed_form(orc):
