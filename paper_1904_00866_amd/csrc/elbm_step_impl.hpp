@@ -515,6 +515,94 @@ __device__ __forceinline__ void S_dS_log(const V& v, R a, R& Sv, R& dS) {
   }
 }
 
+// ln(1 + y) for the root solvers' passes, from the Maclaurin series of
+// artanh: ln(1 + y) = 2 artanh(s) = 2 s (1 + s^2/3 + s^4/5 + ...) with
+// s = y / (2 + y), truncated after K terms.  For |y| <= Log1pK<K>::ymax the
+// first omitted term, s^(2K) / (2K + 1) <= (ymax / (2 - ymax))^(2K) / (2K + 1),
+// is below 2^-54 of the sum; s carries about two roundings (the reciprocal is
+// the refined hardware estimate), so the result is good to about two units
+// in the last place without the range reduction and double-double steps of
+// the library routine (about 140 instructions in FP64).
+template <int K>
+struct Log1pK {
+  static constexpr double ymax = K == 5 ? 0.025 : 0.29;
+  static_assert(K == 5 || K == 10, "tiers: K = 5 (|y| <= 0.025), K = 10 (|y| <= 0.29)");
+  double c[K - 1];  // c[k] = 1 / (2k + 3): the coefficients of s^2 .. s^(2K-2)
+  __device__ __forceinline__ Log1pK() {
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k) c[k] = in_sgpr(1.0 / (2.0 * k + 3.0));
+  }
+  __device__ __forceinline__ double operator()(double y) const {
+    const double s = y * rcp_n<double>(2.0 + y);
+    const double t = s * s;
+    double q = c[K - 2];
+#pragma unroll
+    for (int k = K - 3; k >= 0; --k) q = fma(q, t, c[k]);
+    const double s2 = s + s;
+    return fma(s2 * t, q, s2);  // 2s + 2s (s^2/3 + s^4/5 + ...)
+  }
+};
+
+// S(a) and S'(a) as S_dS_log, but as one unrolled pass over the populations
+// the site holds in registers, with ln(1 + y) from Log1pK<K>: valid while
+// every |(1 - a) x_i| <= Log1pK<K>::ymax (the caller checks this for the
+// whole wavefront).  For D3Q27 (f^eq_i = f01[dx][dy] e2[dz]) the sums over
+// c_z are formed with e2 and multiplied by f01 once per (c_x, c_y).
+template <int K, class V, class R>
+__device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS) {
+  constexpr int Q = V::Q;
+  const Log1pK<K> ln1p;
+  const auto P = v.pass_opaque();
+  const R c = R(1) - a;
+  Sv = R(0);
+  dS = R(0);
+  if constexpr (V::kZFactor) {
+#pragma unroll
+    for (int dxy = 0; dxy < 9; ++dxy) {
+      R iS = R(0), iD = R(0);
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        const R xi = v.x(dxy + 9 * dz, P);
+        const R y = c * xi;
+        const R l = ln1p(y);
+        iS = fma(P.e2[dz], fma(R(1) + y, l, -y), iS);
+        iD = fma(P.e2[dz] * xi, l, iD);
+      }
+      Sv = fma(v.f01[dxy % 3][dxy / 3], iS, Sv);
+      dS = fma(-v.f01[dxy % 3][dxy / 3], iD, dS);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R xi = v.x(i, P);
+      const R fi = v.fe(i, P);
+      const R y = c * xi;
+      const R l = ln1p(y);
+      Sv = fma(fi, fma(R(1) + y, l, -y), Sv);
+      dS = fma(-fi * xi, l, dS);
+    }
+  }
+}
+
+// S(a), S'(a) for one Newton iteration: the unrolled register passes when
+// every active lane's |(1 - a) x_i| fits a series tier (xabs = max_i |x_i|
+// of the lane), else the rolled pass with the library logarithm.
+template <class V, class R>
+__device__ __forceinline__ void S_dS_newton(const V& v, R a, R xabs, R& Sv, R& dS) {
+  if constexpr (std::is_same<R, double>::value) {
+    const R yb = fabs(R(1) - a) * xabs;
+    if (__all(yb <= R(Log1pK<5>::ymax))) {
+      S_dS_series<5>(v, a, Sv, dS);
+      return;
+    }
+    if (__all(yb <= R(Log1pK<10>::ymax))) {
+      S_dS_series<10>(v, a, Sv, dS);
+      return;
+    }
+  }
+  S_dS_log(v, a, Sv, dS);
+}
+
 // The rare path of one lane: the long series when alpha_* = 2 and
 // max|x| <= thrL, else the log1p forms.
 template <class V, class R>
@@ -758,7 +846,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
       alpha = R(-1);
       for (int k = 1; k <= d.root_max_iter; ++k) {
         R Sv, dS;
-        S_dS_log(v, a, Sv, dS);
+        S_dS_newton(v, a, xabs, Sv, dS);
         const R gv = Sv - Dv;
         iters = k;
         if (gv == R(0)) {
@@ -1399,9 +1487,14 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
 // common path fits in that budget, so that four waves per SIMD hide the
 // memory latency; the root solvers and FP64 storage keep the registers
 // they need.
+#ifndef ELBM_NEWTON_WAVES
+#define ELBM_NEWTON_WAVES 3
+#endif
 template <class S, int MODE>
 constexpr int step_waves() {
-  return (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) ? 4 : 1;
+  if (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) return 4;
+  if (sizeof(typename S::T) <= 4 && MODE == kNewton) return ELBM_NEWTON_WAVES;
+  return 1;
 }
 
 template <int D, class S, int MODE, class R, bool SUMS>

@@ -66,6 +66,11 @@ def test_one_step_fp64(gpu, orc, D, mode):
         assert abs(st["n_accept2"] - d["n_accept2"]) <= 2
         assert st["n_alphastar_lt2"] == d["n_alphastar_lt2"]
     assert abs(st["sum_rho"] - d["sum_rho"]) <= 1e-13 * d["sum_rho"]
+    if mode != "bgk":
+        # Eq. (6)'s sum: the kernel's H(f^eq) + D against the literal Eq. (3),
+        # to 1e-14 of the size of the summed terms (the sum itself cancels)
+        scale = H.entropy_scale(f0, H.textbook_weights(D))
+        assert abs(st["sum_H"] - d["sum_H"]) <= 1e-14 * scale
     sim.close()
 
 
@@ -89,6 +94,77 @@ def test_one_step_fp64_bisection(gpu, orc, D):
         g = orc.G(D, f0[:, s], ag[s])
         assert -1e-13 - 1e-16 <= g <= 1e-16
     sim.close()
+
+
+FAR_SHAPES = {"ragged": {2: (37, 23, 1), 3: (11, 9, 7)},
+              "rows": {2: (128, 6, 1), 3: (64, 5, 3)}}  # rows: nx % 64 == 0
+
+
+def _source_sites(D, shape):
+    """[Q, N] index of the site x - c_i (periodic) whose collision gives the
+    streamed population i at site x."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
+    c = H.abi_velocities(D)
+    return np.stack([((x - ci[0]) % nx) + nx * (((y - ci[1]) % ny) + ny * ((z - ci[2]) % nz))
+                     for ci in c])
+
+
+def _far_mixed_state(D, N, seed):
+    """Half the sites far from equilibrium (deviation size 0.7, tilt 0.2:
+    alpha_* = alpha_max < 2 at many of them), the others with deviations
+    log-uniform in [7e-4, 0.7], so that every tier of the closed form (the
+    3-, 4- and 14-term series, the log1p forms at alpha_* = 2 and alpha_* <
+    2) meets inside the same wavefronts."""
+    W = H.textbook_weights(D)
+    far = Wk.random_populations(W, N, 0.7, seed, tilt=0.2)
+    mix = Wk.random_populations(W, N, 0.7, seed + 1, tilt=0.2, log_uniform_eps=True)
+    pick = np.random.default_rng(seed + 2).random(N) < 0.5
+    return np.ascontiguousarray(np.where(pick[None, :], far, mix))
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("box", ["ragged", "rows"])
+@pytest.mark.parametrize("mode", ["closed", "secant", "newton", "bisect"])
+def test_one_step_fp64_far_from_equilibrium(gpu, orc, D, box, mode):
+    """FP64 one-step parity where alpha_* = alpha_max < 2 (Eq. (8)) on more
+    than 5 % of the sites and the deferred rare path (long series, log1p
+    forms) runs: populations within 1e-12, alpha within 1e-11, the alpha_* < 2
+    count equal, and sum_x H (Eq. (6), from the kernel's H(f^eq) + D) within
+    1e-14 of sum_x sum_i |f_i ln(f_i/W_i)| of the oracle's literal sum of
+    Eq. (3).  Bisection stops anywhere in its window -tol <= G <= 0: where
+    the two alphas differ (the midpoints took another turn), the GPU's is
+    checked against the window with the oracle's G."""
+    shape = FAR_SHAPES[box][D]
+    N = int(np.prod(shape))
+    f0 = _far_mixed_state(D, N, seed=5200 + 10 * D + len(box) + len(mode))
+    sim = _sim(gpu, D, shape, f0, storage="f64", beta=0.9, mode=mode,
+               diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS | gpu.DIAG_SUMS)
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    st = sim.stats()
+    sim.close()
+    cfg = _ocfg(orc, D, shape, beta=0.9, mode=mode, root_max_iter=200)
+    fo, ao, d = orc.step(cfg, f0, want_alpha=True, want_diag=True)
+    assert d["n_alphastar_lt2"] > N // 20
+    assert st["n_alphastar_lt2"] == d["n_alphastar_lt2"]
+    scale = H.entropy_scale(f0, H.textbook_weights(D))
+    assert abs(st["sum_H"] - d["sum_H"]) <= 1e-14 * scale, (st["sum_H"], d["sum_H"], scale)
+    assert abs(st["sum_rho"] - d["sum_rho"]) <= 1e-13 * d["sum_rho"]
+    rel = np.abs(fg - fo) / np.abs(fo)
+    if mode == "bisect":
+        same = np.abs(ag - ao) <= 1e-14
+        assert same.mean() > 0.9
+        # after streaming, population (i, x) was collided at x - c_i
+        assert np.max(rel[same[_source_sites(D, shape)]]) <= 1e-12
+        for s in np.nonzero(~same)[0]:
+            g = orc.G(D, f0[:, s], ag[s])
+            assert -1e-13 - 1e-16 <= g <= 1e-16, (s, g)
+    else:
+        assert np.max(rel) <= 1e-12, np.max(rel)
+        assert np.max(np.abs(ag - ao)) <= 1e-11
 
 
 def test_w1_taylor_green_1000_steps_fp64(gpu, orc):
@@ -481,6 +557,13 @@ def test_d3q27_multistep_fp64_ragged(gpu, orc):
     fg = sim.populations().cpu().numpy()
     assert np.max(np.abs(fg - fo) / np.abs(fo)) <= 1e-12
     assert np.all(np.diff(Hs) <= 1e-12 * abs(Hs[0]))
+    # sum_x H of the next step's pre-collision state (the GPU's own f(50)):
+    # the kernel's H(f^eq) + D against the oracle's literal Eq. (3) sum on
+    # the same state
+    sim.step(1)
+    _, _, d1 = orc.step(cfg, fg, want_diag=True)
+    scale = H.entropy_scale(fg, H.textbook_weights(3))
+    assert abs(sim.stats()["sum_H"] - d1["sum_H"]) <= 1e-14 * scale
     sim.close()
 
 
