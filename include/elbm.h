@@ -270,6 +270,33 @@ const char *elbm_last_error(void);
 elbm_status elbm_step_batch(elbm_sim *const *sims, const int64_t *nsteps,
                             int32_t n);
 
+/* ---- a step with diagnostics that allocates nothing ---------------------
+ *
+ * For callers that cannot allocate device memory or hand the library a
+ * workspace: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  It is elbm_step(sim, nsteps) followed by
+ * elbm_stats for a handle whose state need not hold the diagnostics areas
+ * (create it without ELBM_DIAG_COUNTS): the per-workgroup records of the
+ * steps live in a device array the library holds for the life of the
+ * process, one per GPU (7,340,032 bytes: records of at most 65,536
+ * workgroups of 256 sites, so boxes of at most 16,777,216 sites), and the
+ * diagnostics of the last step are reduced into dev_stats.
+ *   diag:      ELBM_DIAG_COUNTS, optionally | ELBM_DIAG_SUMS (the meaning of
+ *              each field as for elbm_stats); the handle's own
+ *              ELBM_DIAG_ALPHA setting still records alpha(x).
+ *   dev_stats: DEVICE pointer to one elbm_stats_t, written on the handle's
+ *              stream after the last step (no host copy, no synchronisation,
+ *              no allocation, no memset).
+ * Populations, alpha and the statistics are the same bits as elbm_step then
+ * elbm_stats.  Afterwards elbm_stats on the handle returns ELBM_ESTATE until
+ * an elbm_step has written the handle's own records.  All calls on one GPU
+ * share its array: calls that overlap on that GPU (other streams, other
+ * threads) race and corrupt each other's statistics; serialise them.
+ * ELBM_EINVAL for nsteps < 1, a NULL pointer, other diag bits, or a box of
+ * more than 65,536 workgroups (message names the limit). */
+elbm_status elbm_step_noalloc(elbm_sim *sim, int64_t nsteps, uint32_t diag,
+                              elbm_stats_t *dev_stats);
+
 /* ---- serving: continuous batching of many simulations ------------------
  *
  * A server owns a scheduler thread and sub-allocates the states of the

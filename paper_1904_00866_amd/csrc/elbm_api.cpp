@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,6 +49,46 @@ constexpr int64_t kMaxDim = (1 << 20) - 1;  // site-coordinate arithmetic limit
 constexpr int64_t kMaxSites = (int64_t(1) << 31) - 1;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---- the diagnostics scratch of elbm_step_noalloc ---------------------------
+// A file-scope device array that holds the per-workgroup diagnostics records
+// (counts, then sums) of the steps elbm_step_noalloc runs, so that it needs
+// no workspace from the caller.  Every GPU the library runs on holds its own
+// copy (kScratchBytes) until the process ends.  In host code `scratch` names
+// a host-side stand-in, not device memory: kernels get the device's own
+// address, looked up once per device with that device current.
+constexpr int kScratchBlocks = 65536;  // workgroup records: up to 2^24 sites
+constexpr size_t kScratchCountBytes = size_t(kScratchBlocks) * kCountBytes;
+constexpr size_t kScratchBytes = kScratchCountBytes + size_t(kScratchBlocks) * kSumBytes;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// The address of `scratch` on device dev, which must be the current device;
+// looked up on the first call for that device and kept.
+hipError_t scratch_on(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? p : nullptr;
+  });
+  *out = g_scratch_ptr[dev];
+  return g_scratch_err[dev];
+}
+
+// step and n_sites of a device elbm_stats_t (the rest comes from k_reduce)
+__global__ void k_stats_header(elbm_stats_t* out, int64_t step, int64_t n_sites) {
+  out->step = step;
+  out->n_sites = n_sites;
+}
+static_assert(offsetof(elbm_stats_t, n_sites) == 8 && offsetof(elbm_stats_t, sum_H) ==
+                  8 + offsetof(Reduced, H) && sizeof(elbm_stats_t) == 8 + sizeof(Reduced),
+              "Reduced is elbm_stats_t after its step field");
 
 int elem_size(int storage) {
   switch (storage) {
@@ -351,6 +393,12 @@ elbm_status elbm::init_sim(const elbm_config* cfg, const double* rho0, const dou
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  {
+    // set-up of the no-allocation step's scratch on this device (a failed
+    // lookup is reported by elbm_step_noalloc, which is its only user)
+    void* p;
+    (void)scratch_on(dev, &p);
+  }
   elbm_sim* s = new_handle(cfg, L, dev_state, hip_stream, dev);
   if (!s) return fail(ELBM_EINVAL, "out of host memory");
 
@@ -506,6 +554,49 @@ elbm_status elbm_step_batch(elbm_sim* const* sims, const int64_t* nsteps, int32_
       for (size_t k = c0; k < c1; ++k) after_step(active[k]);
     }
   }
+  return ELBM_OK;
+}
+
+elbm_status elbm_step_noalloc(elbm_sim* s, int64_t nsteps, uint32_t diag,
+                              elbm_stats_t* dev_stats) {
+  elbm_status st = check_sim(s);
+  if (st != ELBM_OK) return st;
+  if (nsteps < 1) return fail(ELBM_EINVAL, "nsteps < 1");
+  if (!dev_stats) return fail(ELBM_EINVAL, "dev_stats is NULL");
+  if (!(diag & ELBM_DIAG_COUNTS) || (diag & ~(uint32_t)(ELBM_DIAG_COUNTS | ELBM_DIAG_SUMS)))
+    return fail(ELBM_EINVAL, "diag must be ELBM_DIAG_COUNTS, optionally with ELBM_DIAG_SUMS");
+  if (s->L.nblocks > kScratchBlocks)
+    return fail(ELBM_EINVAL,
+                "%lld sites need %d workgroup records; the static scratch holds %d "
+                "(at most %lld sites)",
+                (long long)s->L.N, s->L.nblocks, kScratchBlocks,
+                (long long)kScratchBlocks * kBlock * tiles_per_block(s->L.esize));
+  DeviceGuard g(s->device);
+  if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
+  void* p = nullptr;
+  hipError_t e = scratch_on(s->device, &p);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  char* counts = static_cast<char*>(p);
+  char* sums = (diag & ELBM_DIAG_SUMS) ? counts + kScratchCountBytes : nullptr;
+  BatchArgs a;
+  a.n = 1;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    a.d[0] = desc_of(s, 0);
+    a.d[0].counts = counts;
+    a.d[0].sums = sums;
+    a.d[0].diag = int((s->cfg.diag & ELBM_DIAG_ALPHA) | diag);
+    if ((e = s->launch(a, s->L.nblocks, s->stream)) != hipSuccess)
+      return hip_fail(e, "step kernel launch");
+    after_step(s);
+  }
+  // the handle's own records were not written by these steps
+  s->have_stats = false;
+  if ((e = launch_reduce(counts, sums, s->L.nblocks,
+                         reinterpret_cast<Reduced*>(reinterpret_cast<char*>(dev_stats) + 8),
+                         s->stream)) != hipSuccess)
+    return hip_fail(e, "diagnostics reduction");
+  k_stats_header<<<1, 1, 0, s->stream>>>(dev_stats, s->t, s->L.N);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "diagnostics header");
   return ELBM_OK;
 }
 

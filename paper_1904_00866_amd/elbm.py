@@ -38,7 +38,7 @@ EXPORTS = ["elbm_config_default", "elbm_state_bytes", "elbm_init", "elbm_set_pop
            "elbm_server_poll", "elbm_server_wait", "elbm_server_sim", "elbm_server_release",
            "elbm_server_cancel",
            "elbm_server_get_stats", "elbm_server_destroy", "elbm_checkpoint_bytes",
-           "elbm_export", "elbm_import"]
+           "elbm_export", "elbm_import", "elbm_step_noalloc"]
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
@@ -135,6 +135,7 @@ def lib():
         L.elbm_checkpoint_bytes.restype = C.c_size_t
         L.elbm_export.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_int64)]
         L.elbm_import.argtypes = [vp, vp, C.c_size_t, C.c_int64]
+        L.elbm_step_noalloc.argtypes = [vp, C.c_int64, C.c_uint32, vp]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or C.c_int
         L.elbm_state_bytes.restype = C.c_size_t
@@ -282,12 +283,30 @@ class Simulation:
     def stats(self) -> dict:
         s = Stats()
         _check(lib().elbm_stats(self.handle, C.byref(s)))
-        return dict(step=s.step, n_sites=s.n_sites, n_accept2=s.n_accept2,
-                    n_alphastar_lt2=s.n_alphastar_lt2, n_alpha_lt2=s.n_alpha_lt2,
-                    n_guard=s.n_guard, n_fallback=s.n_fallback, n_negative=s.n_negative,
-                    n_nonfinite=s.n_nonfinite, total_iters=s.total_iters,
-                    alpha_min=s.alpha_min, alpha_max=s.alpha_max, sum_rho=s.sum_rho,
-                    sum_j=list(s.sum_j), sum_H=s.sum_H)
+        return stats_dict(s)
+
+    def step_noalloc(self, n: int, diag: int, dev_stats: torch.Tensor):
+        """elbm_step_noalloc: n steps, the last step's diagnostics into
+        dev_stats (a device tensor of STATS_BYTES bytes) on the stream."""
+        assert dev_stats.device.type == "cuda" and dev_stats.nbytes >= STATS_BYTES
+        _check(lib().elbm_step_noalloc(self.handle, int(n), int(diag), _ptr(dev_stats)))
+
+
+STATS_BYTES = C.sizeof(Stats)
+
+
+def stats_dict(s: Stats) -> dict:
+    return dict(step=s.step, n_sites=s.n_sites, n_accept2=s.n_accept2,
+                n_alphastar_lt2=s.n_alphastar_lt2, n_alpha_lt2=s.n_alpha_lt2,
+                n_guard=s.n_guard, n_fallback=s.n_fallback, n_negative=s.n_negative,
+                n_nonfinite=s.n_nonfinite, total_iters=s.total_iters,
+                alpha_min=s.alpha_min, alpha_max=s.alpha_max, sum_rho=s.sum_rho,
+                sum_j=list(s.sum_j), sum_H=s.sum_H)
+
+
+def stats_from_bytes(raw) -> dict:
+    """An elbm_stats_t copied out of device memory (bytes or a uint8 array)."""
+    return stats_dict(Stats.from_buffer_copy(bytes(raw)[:STATS_BYTES]))
 
 
 def step_batch(sims, nsteps):

@@ -192,6 +192,7 @@ def test_init_argument_errors_before_device_work():
     t = C.c_int64()
     assert L.elbm_export(None, None, 0, C.byref(t)) == -1
     assert L.elbm_import(None, None, 0, 0) == -1
+    assert L.elbm_step_noalloc(None, 1, elbm.DIAG_COUNTS, None) == -1
 
 
 def test_batch_argument_errors():
