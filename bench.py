@@ -9,10 +9,13 @@ with the per-step counters (accepted alpha = 2, alpha range, mass, momentum)
 on.  Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line on stdout: MLUPS (value), the HBM roofline of the step
-kernel, the Newton-alpha and BGK comparisons on the same box, and the CPU
+kernel, the Newton-alpha and BGK comparisons on the same box, a second timing
+window late in the run (t near 5000), the serving streams, and the CPU
 oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--n 512]
+    python bench.py --lattice d2q9 --n 4096 --only closed ...   (profiling
+        runs of the D2Q9 kernels: the doubly periodic shear layer, Re = 3e4)
 """
 from __future__ import annotations
 
@@ -70,39 +73,78 @@ def measured_traffic(workload_key: str):
     return rec.get("bytes_per_launch")
 
 
-def time_mode(elbm, torch, n, storage, beta, mode, steps, warmup, diag, rho, u, arith="fp64"):
-    sim = elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, device="cuda:0",
-                          storage=storage, beta=beta, mode=mode, diag=diag,
-                          root_max_iter=200, fp64=arith)
-    stream = sim.stream
-    sim.step(warmup)
-    torch.cuda.synchronize()
+def _window(torch, sim, steps):
+    """ms per step of `steps` steps, from HIP events on the launch stream."""
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    t0.record(stream)
+    t0.record(sim.stream)
     sim.step(steps)
-    t1.record(stream)
+    t1.record(sim.stream)
     torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def time_mode(elbm, torch, box, storage, beta, mode, steps, warmup, diag, rho, u, arith="fp64",
+              late_to=0, late_steps=50, checkpoint=None):
+    """Warm-up, then one timed window of `steps` steps; with late_to > 0 the
+    run continues (untimed) to t = late_to and times a second window of
+    late_steps steps there.  With checkpoint = (blob, t) the simulation
+    starts from that stored state (elbm_import) instead of t = 0."""
+    lattice, dims = box
+    sim = elbm.Simulation(lattice, *dims, rho0=rho, u0=u, device="cuda:0",
+                          storage=storage, beta=beta, mode=mode, diag=diag,
+                          root_max_iter=200, fp64=arith)
+    if checkpoint is not None:
+        sim.import_(*checkpoint)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t_start = sim.t
+    ms = _window(torch, sim, steps)
     wall = time.perf_counter() - w0
-    ms = t0.elapsed_time(t1)
     stats = sim.stats() if diag & elbm.DIAG_COUNTS else None
+    if stats is not None:
+        stats["t_start"] = t_start
+    late = None
+    if late_to > sim.t + late_steps:
+        sim.step(late_to - late_steps - sim.t)
+        torch.cuda.synchronize()
+        ckpt = sim.export()  # the late state, for the comparison modes
+        t_late = sim.t
+        late_ms = _window(torch, sim, late_steps)
+        late = {"t_start": t_late, "steps": late_steps, "ms_per_step": round(late_ms, 4),
+                "stats": sim.stats() if diag & elbm.DIAG_COUNTS else None,
+                "checkpoint": ckpt}
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return ms / steps, wall, stats
+    return ms, wall, stats, late
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def cpu_baseline(n_full, beta, budget_s=10.0):
     """The FP64 oracle as it stands, OpenMP over sites, on a 128^3 sample of
-    the same Taylor-Green workload, for about budget_s seconds."""
+    the same Taylor-Green workload, for about budget_s seconds on the host
+    threads this process may use (at most 16, the host share of one GPU on a
+    shared box), then on one thread."""
     import oracle
     from paper_1904_00866_amd import workloads as Wk
+    nproc = os.cpu_count() or 1
     try:
-        cores = len(os.sched_getaffinity(0))
+        allowed = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        allowed = nproc
+    cores = max(1, min(allowed, 16))
     m = 128
     rho, u = Wk.taylor_green_3d(m)
     cfg = oracle.Config(D=3, nx=m, ny=m, nz=m, beta=beta, nthreads=cores)
@@ -125,12 +167,26 @@ def cpu_baseline(n_full, beta, budget_s=10.0):
         if eln >= budget_s / 3 or nsteps >= 100:
             break
     newton = m ** 3 * nsteps / eln / 1e6
+    # one thread, the same sample, about a fifth of the budget
+    cfg1 = oracle.Config(D=3, nx=m, ny=m, nz=m, beta=beta, nthreads=1)
+    s1, t0 = 0, time.perf_counter()
+    while True:
+        f, _, _ = oracle.step(cfg1, f)
+        s1 += 1
+        el1 = time.perf_counter() - t0
+        if el1 >= budget_s / 5 or s1 >= 20:
+            break
+    single = m ** 3 * s1 / el1 / 1e6
+    model = cpu_model()
     return {"value": round(closed, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"D3Q27 Taylor-Green {m}^3 (of the {n_full}^3 workload), closed-form "
                       f"alpha, FP64, {steps} steps in {el:.1f} s on {cores} threads "
-                      f"({platform.processor() or platform.machine()}); then Newton alpha, "
-                      f"{nsteps} steps in {eln:.1f} s",
+                      f"({model}; nproc {nproc}, {allowed} allowed to this process); then "
+                      f"Newton alpha, {nsteps} steps in {eln:.1f} s; then closed form on one "
+                      f"thread, {s1} steps in {el1:.1f} s",
+            "cpu_model": model, "nproc": nproc, "cores_allowed": allowed,
+            "single_core_value": round(single, 3),
             "newton_value": round(newton, 3), "closed_over_newton": round(closed / newton, 2)}
 
 
@@ -200,7 +256,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--lattice", default="d3q27", choices=["d3q27", "d2q9"],
+                    help="d3q27: the 3-D Taylor-Green vortex n^3 (the benchmark); d2q9: the "
+                         "doubly periodic shear layer n^2 (Re = 3e4), for profiling runs")
+    ap.add_argument("--n", type=int, default=None,
+                    help="box edge (default 512 for d3q27, 4096 for d2q9)")
+    ap.add_argument("--late-t", type=int, default=5000,
+                    help="also time a window of 50 closed-form steps ending at t = late_t "
+                         "(the end of the 5000-step workload; 0: skip)")
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES))
     ap.add_argument("--arith", default="fp64", choices=sorted(ARITH),
                     help="site arithmetic: fp64 (default), or for the closed form mixed "
@@ -210,12 +273,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None, choices=["closed", "newton", "bisect", "bgk"],
                     help="time one alpha mode only (profiling runs)")
-    ap.add_argument("--serving-requests", type=int, default=64,
+    ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the Poisson serving stream (0: skip serving)")
     ap.add_argument("--serving-rate", type=float, default=20.0)
-    ap.add_argument("--serving-steady-requests", type=int, default=24)
-    ap.add_argument("--serving-steady-rate", type=float, default=3.0,
-                    help="arrival rate of the second stream, below capacity")
+    ap.add_argument("--serving-steady-requests", type=int, default=120)
+    ap.add_argument("--serving-steady-rate", type=float, default=4.0,
+                    help="arrival rate of the second stream, about 0.7 of the measured "
+                         "serving capacity (mean request 1.17e10 site updates)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (a known-size kernel "
                          "that calibrates hardware byte counters in profiling runs)")
@@ -249,11 +313,23 @@ def main() -> int:
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
         del a, b
         torch.cuda.empty_cache()
-    n, storage = args.n, args.storage
-    N = n ** 3
-    beta = Wk.tgv3d_beta(n)
-    log(f"building {n}^3 Taylor-Green fields")
-    rho, u = Wk.taylor_green_3d(n)
+    storage = args.storage
+    three_d = args.lattice == "d3q27"
+    n = args.n or (512 if three_d else 4096)
+    if three_d:
+        N, Q, dims = n ** 3, 27, (n, n, n)
+        beta = Wk.tgv3d_beta(n)
+        log(f"building {n}^3 Taylor-Green fields")
+        rho, u = Wk.taylor_green_3d(n)
+        workload = (f"D3Q27 ELBM Taylor-Green vortex {n}^3 periodic, u0=0.05, Re=1600")
+    else:
+        N, Q, dims = n * n, 9, (n, n, 1)
+        beta = Wk.shear_beta(n)
+        log(f"building {n}^2 shear-layer fields")
+        rho, u = Wk.shear_layer(n)
+        workload = (f"D2Q9 ELBM doubly periodic shear layer {n}^2, u0=0.04, kappa=80, "
+                    f"delta=0.05, Re=3e4")
+    box = (args.lattice, dims)
     diag = elbm.DIAG_COUNTS
     results = {}
     modes = [args.only] if args.only else (["closed"] if args.no_compare
@@ -261,21 +337,39 @@ def main() -> int:
     for mode in modes:
         steps = args.steps if mode in ("closed", "bgk") else args.compare_steps
         warm = args.warmup if mode in ("closed", "bgk") else 2
-        log(f"{mode}: warmup {warm}, timing {steps} steps")
-        ms, wall, st = time_mode(elbm, torch, n, storage, beta, mode, steps, warm, diag, rho, u,
-                                 args.arith)
-        results[mode] = dict(ms=ms, wall=wall, stats=st, steps=steps)
-        log(f"{mode}: {ms:.3f} ms/step, {N / ms / 1e3:.0f} MLUPS")
+        late_to = args.late_t if (mode == "closed" and not args.only and three_d) else 0
+        log(f"{mode}: warmup {warm}, timing {steps} steps"
+            + (f", then a window ending at t = {late_to}" if late_to else ""))
+        ms, wall, st, late = time_mode(elbm, torch, box, storage, beta, mode, steps, warm, diag,
+                                       rho, u, args.arith, late_to=late_to)
+        results[mode] = dict(ms=ms, wall=wall, stats=st, steps=steps, late=late)
+        log(f"{mode}: {ms:.3f} ms/step, {N / ms / 1e3:.0f} MLUPS"
+            + (f"; at t = {late['t_start']}: {late['ms_per_step']:.3f} ms/step" if late else ""))
+    # Newton on the closed form's late state (the same state as its late
+    # window): the comparison where the flow has developed
+    late = results.get("closed", {}).get("late")
+    if late and "newton" in results:
+        ckpt = late.pop("checkpoint")
+        log(f"newton on the state at t = {ckpt[1]}: timing {args.compare_steps} steps")
+        ms_n, _, st_n, _ = time_mode(elbm, torch, box, storage, beta, "newton", args.compare_steps,
+                                     1, diag, rho, u, args.arith, checkpoint=ckpt)
+        results["newton_late"] = dict(ms=ms_n, stats=st_n, steps=args.compare_steps)
+        log(f"newton late: {ms_n:.3f} ms/step")
+        del ckpt
+        torch.cuda.empty_cache()
+    elif late:
+        late.pop("checkpoint", None)
     del rho, u
 
     main_mode = args.only or "closed"
     r = results[main_mode]
     ms = r["ms"]
     mlups = N / (ms * 1e-3) / 1e6
-    Q, b = 27, BYTES[storage]
+    b = BYTES[storage]
     alg_bytes = 2 * Q * b * N  # read + write every population once per step
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    key = f"d3q27_{n}_{storage}_{main_mode}" + ("" if args.arith == "fp64" else f"_{args.arith}")
+    key = f"{args.lattice}_{n}_{storage}_{main_mode}" + ("" if args.arith == "fp64"
+                                                         else f"_{args.arith}")
     traffic = measured_traffic(key)
     out = {
         "metric": METRIC,
@@ -290,34 +384,57 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": ARITH[args.arith][0],
         "data": "synthetic (analytic Taylor-Green initial field)",
-        "config": {"workload": f"D3Q27 ELBM Taylor-Green vortex {n}^3 periodic, "
-                               f"{storage.upper()} population storage, {ARITH[args.arith][1]} site "
-                               f"arithmetic, "
-                               f"u0=0.05, Re=1600, {main_mode} alpha",
-                   "lattice": "D3Q27", "n": n, "sites": N, "storage": storage,
+        "config": {"workload": f"{workload}, {storage.upper()} population storage, "
+                               f"{ARITH[args.arith][1]} site arithmetic, {main_mode} alpha",
+                   "lattice": args.lattice.upper(), "n": n, "sites": N, "storage": storage,
                    "beta": beta, "alpha_mode": main_mode, "arithmetic": args.arith,
                    "diagnostics": "counts"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": f"k_step<3,Store{storage},{main_mode},{args.arith}>"},
+                     "kernel": f"k_step<{3 if three_d else 2},Store{storage},{main_mode},"
+                               f"{args.arith}>"},
     }
+
+    def diag_of(st):
+        return {"accept2_fraction": round(st["n_accept2"] / N, 4),
+                "alpha_lt2_fraction": round(st["n_alpha_lt2"] / N, 4),
+                "alpha_min": st["alpha_min"],
+                "fallback_fraction": st["n_fallback"] / N,
+                "negative_populations": st["n_negative"],
+                "nonfinite_populations": st["n_nonfinite"]}
+
     st = r["stats"]
     if st:
-        out["diagnostics"] = {"accept2_fraction": round(st["n_accept2"] / N, 4),
-                              "alpha_lt2_fraction": round(st["n_alpha_lt2"] / N, 4),
-                              "alpha_min": st["alpha_min"],
-                              "negative_populations": st["n_negative"],
-                              "nonfinite_populations": st["n_nonfinite"]}
+        out["diagnostics"] = dict(diag_of(st), at_step=st["step"])
+    late = r.get("late")
+    if late:
+        out["late_window"] = {"t_start": late["t_start"], "steps": late["steps"],
+                              "ms_per_step": late["ms_per_step"],
+                              "mlups": round(N / late["ms_per_step"] / 1e3, 1),
+                              "diagnostics": diag_of(late["stats"]) if late["stats"] else None}
     if "newton" in results or "bgk" in results:
         cmp = {}
         if "newton" in results:
-            cmp["newton_mlups"] = round(N / results["newton"]["ms"] / 1e3, 1)
-            cmp["closed_over_newton"] = round(results["newton"]["ms"] / ms, 2)
-            stn = results["newton"]["stats"]
+            rn = results["newton"]
+            stn = rn["stats"]
+            cmp["newton_mlups"] = round(N / rn["ms"] / 1e3, 1)
+            cmp["closed_over_newton"] = round(rn["ms"] / ms, 2)
+            cmp["newton_window"] = (f"t = {stn['t_start']} .. {stn['t_start'] + rn['steps']}"
+                                    if stn else None)
             if stn:
                 cmp["newton_iters_per_site"] = round(stn["total_iters"] / N, 3)
+        if "newton_late" in results and r.get("late"):
+            rl = results["newton_late"]
+            stl = rl["stats"]
+            cmp["late"] = {"t_start": stl["t_start"] if stl else None,
+                           "closed_ms": r["late"]["ms_per_step"],
+                           "newton_ms": round(rl["ms"], 4),
+                           "newton_mlups": round(N / rl["ms"] / 1e3, 1),
+                           "closed_over_newton": round(rl["ms"] / r["late"]["ms_per_step"], 2),
+                           "newton_iters_per_site": (round(stl["total_iters"] / N, 3)
+                                                     if stl else None)}
         if "bgk" in results:
             cmp["bgk_mlups"] = round(N / results["bgk"]["ms"] / 1e3, 1)
             cmp["closed_over_bgk_time"] = round(ms / results["bgk"]["ms"], 3)

@@ -41,6 +41,7 @@
  */
 #include "elbm_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -533,11 +534,15 @@ static double solve_bisect(const lat_t *L, const double *feq, const double *x,
 /* Bracketed Newton iteration for the root of Eq. (4) on [1, alpha_max],
  * started at alpha_* (at the bracket midpoint when alpha_* = alpha_max, where
  * G' is unbounded).  A step that leaves the bracket is replaced by the
- * midpoint; the iteration stops at a step (Newton or midpoint) below
- * 1e-13 alpha: the FP64 rounding of G near its root already moves alpha by
- * about that much, so smaller steps only follow rounding noise.  A Newton
- * step below that size that rounds onto (or past) the end of the bracket is
- * a converged step too, and stops there instead of restarting bisection.
+ * midpoint.  The iteration stops
+ *   - when |G(a)| is at the rounding level of its own evaluation,
+ *     eps sum_i w_i (|x_i| + |(1 - a) x_i|) (each term w_i phi(y) is formed
+ *     from O(|y|) parts): a is then a root to the accuracy G can be known
+ *     with, and further steps would only follow rounding noise; or
+ *   - at a step (Newton or midpoint) below 1e-13 alpha.
+ * A Newton step below that size that rounds onto (or past) the end of the
+ * bracket is a converged step too, and stops there instead of restarting
+ * bisection.
  *
  * G is convex with G(1) = -D <= 0 and G' > 0 on (1, alpha_max], so G < 0 on
  * [1, root) and G > 0 beyond it, and a Newton step from a point with G < 0
@@ -550,12 +555,14 @@ static double solve_newton(const lat_t *L, const double *feq, const double *x,
                            double amax, double astar, int maxit, int *iters) {
   double lo = 1.0, hi = amax;
   int hi_positive = 0; /* G(hi) > 0 known */
+  double sx = 0.0;     /* sum_i w_i |x_i| */
+  for (int i = 0; i < L->Q; ++i) sx += weight_of(L, feq, i) * fabs(x[i]);
   double a = (astar < amax) ? astar : 0.5 * (lo + hi);
   *iters = 0;
   for (int k = 1; k <= maxit; ++k) {
     double g = G_of(L, feq, x, a);
     *iters = k;
-    if (g == 0.0) return a;
+    if (fabs(g) <= DBL_EPSILON * (1.0 + fabs(1.0 - a)) * sx) return a;
     if (g > 0.0) {
       hi = a;
       hi_positive = 1;

@@ -249,8 +249,13 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
       }
       if (alpha < 0.0) alpha = lo;
     } else if constexpr (MODE == kNewton) {
+      // stops when |G(a)| is at the rounding level of its evaluation,
+      // eps sum_i W_i (|x_i| + |(1 - a) x_i|), or at a step below 1e-13 a
       double lo = 1.0, hi = amax;
       double a = (astar < amax) ? astar : 0.5 * (lo + hi);
+      double sA = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sA += L::W(i) * fabs(v.x[i]);
       for (int k = 1; k <= d.root_max_iter; ++k) {
         double Sv = 0.0, dS = 0.0;
 #pragma unroll
@@ -261,7 +266,7 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
         }
         const double gv = Sv - Dv;
         iters = k;
-        if (gv == 0.0) break;
+        if (fabs(gv) <= 2.220446049250313e-16 * (1.0 + fabs(1.0 - a)) * sA) break;
         if (gv > 0.0) hi = a;
         else lo = a;
         double an = a - gv / dS;

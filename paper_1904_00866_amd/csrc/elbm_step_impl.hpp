@@ -52,6 +52,15 @@ __device__ __forceinline__ R opaque(R v) {
 #ifndef ELBM_SCHED_GROUP
 #define ELBM_SCHED_GROUP 0
 #endif
+// Scheduling fence after each group of directions of a Newton pass (0:
+// none): bounds how many directions' logarithms the scheduler interleaves,
+// and with it the registers they hold.
+#ifndef ELBM_NEWTON_FENCE
+#define ELBM_NEWTON_FENCE 1
+#endif
+#ifndef ELBM_NEWTON_OPAQUE
+#define ELBM_NEWTON_OPAQUE 1
+#endif
 __device__ __forceinline__ void sched_group(int i) {
   if (ELBM_SCHED_GROUP > 0 && i % (ELBM_SCHED_GROUP > 0 ? ELBM_SCHED_GROUP : 1) ==
                                   (ELBM_SCHED_GROUP > 0 ? ELBM_SCHED_GROUP : 1) - 1)
@@ -500,10 +509,12 @@ __device__ __forceinline__ R S_log(const V& v, R a) {
 }
 
 // S(a) and S'(a) = G'(a) = -sum_i f^eq_i x_i ln(1 + (1 - a) x_i).
+// With sA, also sum_i f^eq_i |x_i|.
 template <class V, class R>
-__device__ __forceinline__ void S_dS_log(const V& v, R a, R& Sv, R& dS) {
+__device__ __forceinline__ void S_dS_log(const V& v, R a, R& Sv, R& dS, R* sA = nullptr) {
   Sv = R(0);
   dS = R(0);
+  R sa = R(0);
 #pragma unroll 1
   for (int i = 0; i < V::Q; ++i) {
     R xi, fi;
@@ -512,21 +523,45 @@ __device__ __forceinline__ void S_dS_log(const V& v, R a, R& Sv, R& dS) {
     const R l = dlog_clamped<R>(y);
     Sv += fi * ((y <= R(-1)) ? R(1) : (R(1) + y) * l - y);
     dS -= fi * xi * l;
+    sa = fma(fi, fabs(xi), sa);
   }
+  if (sA) *sA = sa;
 }
 
-// ln(1 + y) for the root solvers' passes, from the Maclaurin series of
-// artanh: ln(1 + y) = 2 artanh(s) = 2 s (1 + s^2/3 + s^4/5 + ...) with
-// s = y / (2 + y), truncated after K terms.  For |y| <= Log1pK<K>::ymax the
-// first omitted term, s^(2K) / (2K + 1) <= (ymax / (2 - ymax))^(2K) / (2K + 1),
-// is below 2^-54 of the sum; s carries about two roundings (the reciprocal is
+constexpr double kEpsF64 = 2.220446049250313e-16;  // 2^-52
+
+// ln(1 + y) for the root solvers' passes, in two tiers, without the range
+// reduction and double-double steps of the library routine (about 140
+// instructions in FP64).
+//
+// Log1pM, |y| <= 0.025: the Maclaurin series y - y^2/2 + y^3/3 - ...
+// through y^10 / 10 by Horner's rule; the first omitted term is below
+// 0.025^10 / 11 < 2^-54 of the sum.
+struct Log1pM {
+  static constexpr double ymax = 0.025;
+  double c[9];  // c[k] = (-1)^(k+1) / (k + 2): the coefficients of y^2 .. y^10
+  __device__ __forceinline__ Log1pM() {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c[k] = in_sgpr((k % 2 ? 1.0 : -1.0) / (k + 2.0));
+  }
+  __device__ __forceinline__ double operator()(double y) const {
+    double p = c[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) p = fma(p, y, c[k]);
+    return fma(y * y, p, y);  // y + y^2 (-1/2 + y/3 - ...)
+  }
+};
+
+// Log1pK<10>, |y| <= 0.29: ln(1 + y) = 2 artanh(s) = 2 s (1 + s^2/3 +
+// s^4/5 + ...) with s = y / (2 + y), truncated after K terms; the first
+// omitted term, s^(2K) / (2K + 1) <= (ymax / (2 - ymax))^(2K) / (2K + 1), is
+// below 2^-54 of the sum.  s carries about two roundings (the reciprocal is
 // the refined hardware estimate), so the result is good to about two units
-// in the last place without the range reduction and double-double steps of
-// the library routine (about 140 instructions in FP64).
+// in the last place.
 template <int K>
 struct Log1pK {
-  static constexpr double ymax = K == 5 ? 0.025 : 0.29;
-  static_assert(K == 5 || K == 10, "tiers: K = 5 (|y| <= 0.025), K = 10 (|y| <= 0.29)");
+  static constexpr double ymax = 0.29;
+  static_assert(K == 10, "one tier: K = 10 (|y| <= 0.29)");
   double c[K - 1];  // c[k] = 1 / (2k + 3): the coefficients of s^2 .. s^(2K-2)
   __device__ __forceinline__ Log1pK() {
 #pragma unroll
@@ -544,22 +579,27 @@ struct Log1pK {
 };
 
 // S(a) and S'(a) as S_dS_log, but as one unrolled pass over the populations
-// the site holds in registers, with ln(1 + y) from Log1pK<K>: valid while
-// every |(1 - a) x_i| <= Log1pK<K>::ymax (the caller checks this for the
-// whole wavefront).  For D3Q27 (f^eq_i = f01[dx][dy] e2[dz]) the sums over
+// the site holds in registers, with ln(1 + y) from LN (Log1pM or
+// Log1pK<10>): valid while every |(1 - a) x_i| <= LN::ymax (the caller
+// checks this for the whole wavefront); also sA = sum_i f^eq_i |x_i|.  For D3Q27 (f^eq_i = f01[dx][dy] e2[dz]) the sums over
 // c_z are formed with e2 and multiplied by f01 once per (c_x, c_y).
-template <int K, class V, class R>
-__device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS) {
+template <class LN, class V, class R>
+__device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS, R& sA) {
   constexpr int Q = V::Q;
-  const Log1pK<K> ln1p;
+  const LN ln1p;
+#if ELBM_NEWTON_OPAQUE
   const auto P = v.pass_opaque();
+#else
+  const auto P = v.pass();
+#endif
   const R c = R(1) - a;
   Sv = R(0);
   dS = R(0);
+  sA = R(0);
   if constexpr (V::kZFactor) {
 #pragma unroll
     for (int dxy = 0; dxy < 9; ++dxy) {
-      R iS = R(0), iD = R(0);
+      R iS = R(0), iD = R(0), iA = R(0);
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz) {
         const R xi = v.x(dxy + 9 * dz, P);
@@ -567,9 +607,14 @@ __device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS) {
         const R l = ln1p(y);
         iS = fma(P.e2[dz], fma(R(1) + y, l, -y), iS);
         iD = fma(P.e2[dz] * xi, l, iD);
+        iA = fma(P.e2[dz], fabs(xi), iA);
       }
       Sv = fma(v.f01[dxy % 3][dxy / 3], iS, Sv);
       dS = fma(-v.f01[dxy % 3][dxy / 3], iD, dS);
+      sA = fma(v.f01[dxy % 3][dxy / 3], iA, sA);
+#if ELBM_NEWTON_FENCE
+      __builtin_amdgcn_sched_barrier(0);
+#endif
     }
   } else {
 #pragma unroll
@@ -580,6 +625,10 @@ __device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS) {
       const R l = ln1p(y);
       Sv = fma(fi, fma(R(1) + y, l, -y), Sv);
       dS = fma(-fi * xi, l, dS);
+      sA = fma(fi, fabs(xi), sA);
+#if ELBM_NEWTON_FENCE
+      if (i % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+#endif
     }
   }
 }
@@ -588,19 +637,23 @@ __device__ __forceinline__ void S_dS_series(const V& v, R a, R& Sv, R& dS) {
 // every active lane's |(1 - a) x_i| fits a series tier (xabs = max_i |x_i|
 // of the lane), else the rolled pass with the library logarithm.
 template <class V, class R>
-__device__ __forceinline__ void S_dS_newton(const V& v, R a, R xabs, R& Sv, R& dS) {
+__device__ __forceinline__ void S_dS_newton(V& v, const SimDesc& d, R a, R xabs, R& Sv, R& dS,
+                                            R& sA) {
   if constexpr (std::is_same<R, double>::value) {
     const R yb = fabs(R(1) - a) * xabs;
-    if (__all(yb <= R(Log1pK<5>::ymax))) {
-      S_dS_series<5>(v, a, Sv, dS);
+    if (__all(yb <= R(Log1pM::ymax))) {
+      S_dS_series<Log1pM>(v, a, Sv, dS, sA);
       return;
     }
     if (__all(yb <= R(Log1pK<10>::ymax))) {
-      S_dS_series<10>(v, a, Sv, dS);
+      S_dS_series<Log1pK<10>>(v, a, Sv, dS, sA);
       return;
     }
   }
-  S_dS_log(v, a, Sv, dS);
+  // the rolled pass re-reads the populations: their source offsets are
+  // formed here, not kept live through the register passes
+  v.w = locate<V::kDim>(d, v.site);
+  S_dS_log(v, a, Sv, dS, &sA);
 }
 
 // The rare path of one lane: the long series when alpha_* = 2 and
@@ -670,7 +723,9 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // The root solvers need alpha_max on every lane; the closed form and the
   // secant need it only where alpha_* < 2, which the tiers below detect.
   constexpr bool kXmax = (MODE == kNewton || MODE == kBisect);
-  if constexpr (MODE == kNewton || MODE == kBisect || MODE == kSecant) v.w = locate<D>(d, v.site);
+  // The rolled passes (rare tier, root solvers) re-read the populations
+  // from the source buffer; their source offsets (v.w) are formed just
+  // before each such pass rather than kept live through the whole update.
   // Common tier: x_i, max|x_i| and the K-term series sums in one pass.
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   if constexpr (PHASE != kPhaseRare) {
@@ -755,7 +810,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   if constexpr (PHASE == kPhaseCommon) {
     if (rare) return o;
   }
-  if (PHASE == kPhaseAll && __any(rare) && !kXmax) v.w = locate<D>(d, v.site);
+  if (PHASE == kPhaseAll && __any(rare)) v.w = locate<D>(d, v.site);
   if (rare && !kXmax) {
     xmax = R(-1);
 #pragma unroll 1
@@ -799,6 +854,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
         // alpha^(k+1) = a_* + G(a_*) / (G(a_*) - G(alpha^(k))) (alpha^(k) - a_*),
         // alpha^(0) = 1, so the first iterate is Eq. (9).
         R a = R(1);
+        v.w = locate<D>(d, v.site);
         for (int k = 0; k < d.secant_iters; ++k) {
           const R Ga = S_log(v, a) - Dv;
           const R an = astar + Gs / (Gs - Ga) * (a - astar);
@@ -810,6 +866,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
       }
     } else if constexpr (MODE == kBisect) {
       // Eq. (4) on [1, alpha_max]; first midpoint with -tol <= G <= 0.
+      v.w = locate<D>(d, v.site);
       if (S_log(v, amax) - Dv <= R(0)) {
         alpha = amax;
       } else {
@@ -836,20 +893,22 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
       // with G < 0 lands at or beyond the root; whether the root lies inside
       // the bracket (G(alpha_max) > 0) is asked only when a step leaves it
       // while its upper end is still alpha_max.  A step leaving the bracket
-      // is replaced by the midpoint; the iteration stops at a step below
-      // 1e-13 alpha (the rounding of G near the root moves alpha by about
-      // that much), and a converged Newton step that rounds onto the end of
-      // the bracket stops there.
+      // is replaced by the midpoint.  The iteration stops when |G(a)| is at
+      // the rounding level of its evaluation, eps sum_i f^eq_i (|x_i| +
+      // |(1 - a) x_i|) (each term is formed from O(|y|) parts), or at a step
+      // below 1e-13 alpha (the rounding of G near the root moves alpha by
+      // about that much); a converged Newton step that rounds onto the end
+      // of the bracket stops there.
       R lo = R(1), hi = amax;
       bool hi_pos = false;  // G(hi) > 0 known
       R a = (astar < amax) ? astar : R(0.5) * (lo + hi);
       alpha = R(-1);
       for (int k = 1; k <= d.root_max_iter; ++k) {
-        R Sv, dS;
-        S_dS_newton(v, a, xabs, Sv, dS);
+        R Sv, dS, sA;
+        S_dS_newton(v, d, a, xabs, Sv, dS, sA);
         const R gv = Sv - Dv;
         iters = k;
-        if (gv == R(0)) {
+        if (fabs(gv) <= R(kEpsF64) * (R(1) + fabs(R(1) - a)) * sA) {
           alpha = a;
           break;
         }
@@ -866,6 +925,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
             break;
           }
           if (!hi_pos) {
+            v.w = locate<D>(d, v.site);
             if (S_log(v, hi) - Dv <= R(0)) {
               alpha = hi;
               break;
