@@ -12,8 +12,13 @@ is needed; its parity with the CPU oracle is established by the GPU tests).
                                  proportion of sites accepting alpha = 2
     python experiments.py w4     D3Q27 256^3 Taylor-Green, 2000 steps, storage
                                  FP64 / FP32 / FP32-dev / FP16-dev under FP64,
-                                 mixed and FP32 site arithmetic: velocity and
-                                 kinetic-energy error vs FP64, per-site H increases
+                                 mixed and FP32 site arithmetic: per-site H
+                                 increases, errors against the FP64-storage
+                                 run; with --w4-out DIR the fields on a
+                                 sub-lattice and the kinetic-energy curve
+    python experiments.py w4cmp --w4-ref REF.npz --w4-out DIR
+                                 those fields against the FP64 oracle's
+                                 reference run (stored arrays only, no GPU)
     python experiments.py w5p    the serving stream (64 requests at 20/s) through
                                  a server with 8 slots, first come first served
                                  and with preemption: latency percentiles, MLUPS
@@ -34,6 +39,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -183,7 +189,19 @@ def _H_site(f, W):
     return (f * torch.log(f / W[:, None])).sum(0)
 
 
-def w4(n=256, T=2000):
+W4_SUB = (4, 4, 8)  # sub-lattice strides in x, y, z of the saved fields
+
+
+def w4_sub_index(n: int) -> np.ndarray:
+    """Site indices s = x + n (y + n z) of the sub-lattice x, y = 0, 4, 8, ...,
+    z = 0, 8, 16, ... (x fastest): where the precision sweep saves its fields
+    for the comparison with the FP64 oracle's reference run."""
+    z, y, x = np.meshgrid(np.arange(0, n, W4_SUB[2]), np.arange(0, n, W4_SUB[1]),
+                          np.arange(0, n, W4_SUB[0]), indexing="ij")
+    return (x + n * (y + n * z)).reshape(-1).astype(np.int64)
+
+
+def w4(n=256, T=2000, out_dir=None):
     beta = Wk.tgv3d_beta(n)
     rho, u = Wk.taylor_green_3d(n)
     N = n ** 3
@@ -201,18 +219,30 @@ def w4(n=256, T=2000):
            f"(beta = {beta:.6f}), {T} steps, closed-form alpha", "cases": {}}
     ref = None
     sites = torch.arange(N, dtype=torch.int64, device="cuda")
+    sub = torch.as_tensor(w4_sub_index(n), device="cuda")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
     for storage, arith in cases:
         name = f"{storage}/{arith}-arith"
+        diag = elbm.DIAG_COUNTS | elbm.DIAG_SUMS | (elbm.DIAG_ALPHA if arith == "mixed" else 0)
         with elbm.Simulation("d3q27", n, n, n, rho0=rho, u0=u, storage=storage, fp64=arith,
-                             beta=beta, diag=elbm.DIAG_COUNTS | elbm.DIAG_SUMS) as sim:
-            Hsum, neg = [], 0
+                             beta=beta, diag=diag) as sim:
+            Hsum, neg, kes = [], 0, []
+            r, v = sim.moments()
+            kes.append([0, _kinetic(r, v)])
             for t in range(0, T, 100):
                 sim.step(100)
                 st = sim.stats()
                 Hsum.append(st["sum_H"])
                 neg = max(neg, st["n_negative"])
-            r, v = sim.moments()
-            ke = _kinetic(r, v)
+                r, v = sim.moments()
+                kes.append([t + 100, _kinetic(r, v)])
+            ke = kes[-1][1]
+            if out_dir:
+                np.savez(os.path.join(out_dir, f"w4_{storage}_{arith}.npz"), n=n, steps=T,
+                         sub_strides=np.array(W4_SUB), rho_sub=r[sub].cpu().numpy(),
+                         u_sub=v[:, sub].cpu().numpy(), kinetic_energy=ke,
+                         ke_curve=np.array(kes), sum_rho=float(r.sum()))
             # per-site H balance of one more step: pre-collision f(x,T) vs the
             # stored post-collision value written at x
             f0 = sim.populations()
@@ -222,6 +252,7 @@ def w4(n=256, T=2000):
             dH = _H_site(f1, W) - _H_site(f0, W)
             tauH = 8 * 2.0 ** -52 * r * torch.clamp(
                 (f0 / r * torch.log(f0 / W[:, None]).abs()).sum(0), min=1.0)
+            lw = (torch.log(f1 / W[:, None]) + 1.0).abs()
             # change of H from rounding each stored value to the storage format
             if storage.endswith("dev"):
                 # s = f/W - rho_ref is rounded: |df| <= W ulp(|s|) / 2, with
@@ -230,28 +261,73 @@ def w4(n=256, T=2000):
                 df = W[:, None] * torch.clamp(s, min=2.0 ** -14) * ulp[storage]
             else:
                 df = f1.abs() * ulp[storage]
-            tauS = ((torch.log(f1 / W[:, None]) + 1.0).abs() * df).sum(0)
+            tauS = (lw * df).sum(0)
             inc_fp64 = int((dH > tauH).sum())
             inc_round = int((dH > tauH + tauS).sum())
-            del f0, f1, dH, tauH, tauS, df
             res = {"kinetic_energy": ke, "negative_population_sites_max": neg,
                    "sum_H_increases_per_100_steps": int((np.diff(Hsum) > 0).sum()),
                    "site_H_increase_beyond_fp64_tol": inc_fp64,
                    "site_H_increase_beyond_storage_rounding": inc_round}
+            if arith == "mixed":
+                # the FP32 rounding of the mixed collision s~ = s + alpha beta
+                # (s^eq - s), relative to its operands (s^eq recovered from the
+                # step's own alpha: s^eq - s = (s~ - s) / (alpha beta)) and to
+                # the FP32 moments that form s^eq
+                a = sim.alpha_field()
+                s0 = f0 / W[:, None] - 1.0
+                s1 = f1 / W[:, None] - 1.0
+                d = (s1 - s0) / (a * beta)
+                seq = s0 + d
+                ws = (W[:, None] * s0.abs()).sum(0)
+                ra = W[:, None] * 2.0 ** -24 * (s1.abs() + 2 * d.abs() + 8 * seq.abs() + 8 * ws)
+                res["site_H_increase_beyond_storage_and_fp32_arith"] = int(
+                    (dH > tauH + tauS + (lw * ra).sum(0)).sum())
+                del a, s0, s1, d, seq, ra
+            del f0, f1, dH, tauH, tauS, df, lw
             if ref is None:
                 ref = (r.clone(), v.clone(), ke)
             else:
                 du = (v - ref[1]).abs()
                 umax = ref[1].abs().max().item()
-                res.update({"u_linf_rel": du.max().item() / umax,
-                            "u_l2_rel": (du.pow(2).sum().sqrt() /
-                                         ref[1].pow(2).sum().sqrt()).item(),
-                            "ke_rel_err": (ke - ref[2]) / ref[2],
-                            "rho_linf": (r - ref[0]).abs().max().item()})
+                res.update({"u_linf_rel_vs_fp64_gpu": du.max().item() / umax,
+                            "u_l2_rel_vs_fp64_gpu": (du.pow(2).sum().sqrt() /
+                                                     ref[1].pow(2).sum().sqrt()).item(),
+                            "ke_rel_err_vs_fp64_gpu": (ke - ref[2]) / ref[2],
+                            "rho_linf_vs_fp64_gpu": (r - ref[0]).abs().max().item()})
             del r, v
             torch.cuda.empty_cache()
         out["cases"][name] = res
         log(f"w4 {name}: {res}")
+    return out
+
+
+def w4cmp(ref_path, run_dir):
+    """The precision sweep's fields against the FP64 oracle's reference run
+    (an .npz written by the oracle's reference script): velocity L-inf and L2
+    errors relative to the largest velocity and to the velocity norm on the
+    saved sub-lattice, density L-inf there, kinetic-energy error over the
+    whole box, and the kinetic-energy curve.  Reads stored arrays only."""
+    refz = np.load(ref_path)
+    n = int(refz["n"])
+    assert np.array_equal(refz["sub_index"], w4_sub_index(n)), "sub-lattices differ"
+    uref, rref, keref = refz["u_sub"], refz["rho_sub"], float(refz["kinetic_energy"])
+    curve_ref = refz["ke_curve"]
+    out = {"experiment": "w4cmp", "reference": os.path.basename(ref_path),
+           "reference_sites_compared": int(uref.shape[1]), "cases": {}}
+    for fn in sorted(os.listdir(run_dir)):
+        if not (fn.startswith("w4_") and fn.endswith(".npz")):
+            continue
+        z = np.load(os.path.join(run_dir, fn))
+        du = np.abs(z["u_sub"] - uref)
+        cur = z["ke_curve"]
+        assert np.array_equal(cur[:, 0], curve_ref[:, 0])
+        out["cases"][fn[3:-4]] = {
+            "u_linf_rel": float(du.max() / np.abs(uref).max()),
+            "u_l2_rel": float(np.sqrt((du ** 2).sum() / (uref ** 2).sum())),
+            "rho_linf": float(np.abs(z["rho_sub"] - rref).max()),
+            "ke_rel_err": float((float(z["kinetic_energy"]) - keref) / keref),
+            "ke_curve_max_rel_err": float(np.max(np.abs(cur[:, 1] - curve_ref[:, 1]) /
+                                                 curve_ref[:, 1]))}
     return out
 
 
@@ -429,7 +505,12 @@ def w5p(n_req=64, rate=20.0, max_active=8, round_steps=50, preempt_rounds=20):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", nargs="+", choices=["w1", "w2", "e2", "w4", "w5p", "f3", "f3burg"])
+    ap.add_argument("which", nargs="+",
+                    choices=["w1", "w2", "e2", "w4", "w4cmp", "w5p", "f3", "f3burg"])
+    ap.add_argument("--w4-out", default=None,
+                    help="w4: directory for the fields on the comparison sub-lattice")
+    ap.add_argument("--w4-ref", default=None,
+                    help="w4cmp: the FP64 oracle reference (.npz of the reference script)")
     ap.add_argument("--w2-steps", type=int, default=20000)
     ap.add_argument("--f3-n", type=int, default=512)
     ap.add_argument("--f3-steps", type=int, default=20)
@@ -441,13 +522,17 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one torch copy of this many MiB first (HBM counter scale)")
     args = ap.parse_args()
+    if args.which == ["w4cmp"]:
+        # reads stored arrays only (no GPU)
+        print(json.dumps(w4cmp(args.w4_ref, args.w4_out)), flush=True)
+        return 0
     if not torch.cuda.is_available():
         print("experiments.py needs a GPU", file=sys.stderr)
         return 1
     elbm.lib()
     for w in args.which:
         t0 = time.time()
-        res = {"w1": w1, "e2": e2, "w4": w4, "w5p": w5p,
+        res = {"w1": w1, "e2": e2, "w4": lambda: w4(out_dir=args.w4_out), "w5p": w5p,
                "f3burg": lambda: f3burg(n3=args.f3_n, steps=args.f3_steps,
                                         tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
                                         cases=[c for c in args.f3burg_cases.split(",") if c]),

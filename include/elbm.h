@@ -279,7 +279,8 @@ elbm_status elbm_step_batch(elbm_sim *const *sims, const int64_t *nsteps,
  * (create it without ELBM_DIAG_COUNTS): the per-workgroup records of the
  * steps live in a device array the library holds for the life of the
  * process, one per GPU (7,340,032 bytes: records of at most 65,536
- * workgroups of 256 sites, so boxes of at most 16,777,216 sites), and the
+ * workgroups, i.e. boxes of at most 2^24 sites, or 2^26 for D1Q3 and D2Q9
+ * with 2- or 4-byte storage, whose workgroups hold 1024 sites), and the
  * diagnostics of the last step are reduced into dev_stats.
  *   diag:      ELBM_DIAG_COUNTS, optionally | ELBM_DIAG_SUMS (the meaning of
  *              each field as for elbm_stats); the handle's own
@@ -293,7 +294,7 @@ elbm_status elbm_step_batch(elbm_sim *const *sims, const int64_t *nsteps,
  * share its array: calls that overlap on that GPU (other streams, other
  * threads) race and corrupt each other's statistics; serialise them.
  * ELBM_EINVAL for nsteps < 1, a NULL pointer, other diag bits, or a box of
- * more than 65,536 workgroups (message names the limit). */
+ * more than 65,536 workgroups (the message names the limit in sites). */
 elbm_status elbm_step_noalloc(elbm_sim *sim, int64_t nsteps, uint32_t diag,
                               elbm_stats_t *dev_stats);
 

@@ -163,7 +163,7 @@ elbm_status check_config(const elbm_config* c, Layout* L) {
   // multiple of 8 (the kernel's XCD-aware tile order needs it).  The count
   // depends only on the box, so per-workgroup diagnostics sum in the same
   // order wherever and however the simulation is stepped.
-  const int64_t tpb = tiles_per_block(es);
+  const int64_t tpb = tiles_per_block(es, L->Q);
   const int64_t ntiles = (N + kBlock - 1) / kBlock;
   const int64_t units = (ntiles + tpb - 1) / tpb;
   L->nblocks = int((units + 7) / 8 * 8);
@@ -570,7 +570,7 @@ elbm_status elbm_step_noalloc(elbm_sim* s, int64_t nsteps, uint32_t diag,
                 "%lld sites need %d workgroup records; the static scratch holds %d "
                 "(at most %lld sites)",
                 (long long)s->L.N, s->L.nblocks, kScratchBlocks,
-                (long long)kScratchBlocks * kBlock * tiles_per_block(s->L.esize));
+                (long long)kScratchBlocks * kBlock * tiles_per_block(s->L.esize, s->L.Q));
   DeviceGuard g(s->device);
   if (!g.ok) return fail(ELBM_EDEVICE, "cannot select the simulation's device");
   void* p = nullptr;

@@ -9,14 +9,21 @@ namespace elbm {
 
 constexpr int kBlock = 256;        // threads per workgroup of the step kernel
 
-// Tiles of kBlock sites per step workgroup.  One: the closed form and LBGK
-// run four waves per SIMD, which hide the memory latency better than a
-// second tile's loads issued ahead within one wave (a build option keeps
-// two for 2- and 4-byte storage).
+// Tiles of kBlock sites per step workgroup, whose loads a wavefront issues
+// before the first tile's arithmetic.  Lattices with 19 or 27 directions:
+// one; they run four waves per SIMD, which hide the memory latency better
+// than a second tile's loads issued ahead within one wave.  Lattices with 3
+// or 9 directions have few loads per site, so more tiles put more bytes in
+// flight per wave (ELBM_TILES_SMALLQ; 2- and 4-byte storage only).
 #ifndef ELBM_TILES_NARROW
 #define ELBM_TILES_NARROW 1
 #endif
-constexpr int tiles_per_block(int elem_bytes) { return elem_bytes < 8 ? ELBM_TILES_NARROW : 1; }
+#ifndef ELBM_TILES_SMALLQ
+#define ELBM_TILES_SMALLQ 4
+#endif
+constexpr int tiles_per_block(int elem_bytes, int Q) {
+  return elem_bytes < 8 ? (Q <= 9 ? ELBM_TILES_SMALLQ : ELBM_TILES_NARROW) : 1;
+}
 constexpr int kMaxBatch = 16;      // simulations per batched launch
 constexpr int kCountBytes = 48;    // per-workgroup counts record
 constexpr int kSumBytes = 64;      // per-workgroup sums record

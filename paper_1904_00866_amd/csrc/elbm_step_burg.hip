@@ -327,7 +327,7 @@ template <class L, class S, int MODE, bool SUMS>
 __global__ void __launch_bounds__(kBlock) k_step_burg(const BatchArgs args) {
   using T = typename S::T;
   constexpr int Q = L::Q;
-  constexpr int ELBM_TILES = tiles_per_block(sizeof(T));
+  constexpr int ELBM_TILES = tiles_per_block(sizeof(T), Q);
   const int b = blockIdx.x;
   int si = 0;
   for (int k = 1; k < args.n; ++k)

@@ -778,10 +778,13 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // D = H(f) - H(f^eq), Gs = H(f*(a_*)) - H(f), Ds = H(f*(a_*)) - H(f^eq); at
   // alpha_* = 2: D = E - O, Ds = E + O, Gs = 2 O.
   R Dv = sE - sO, Ds = sE + sO, Gs = R(2) * sO;
-  // max|x| <= thrM < 1 implies max x <= 1, i.e. alpha_* = 2.
-  const bool common = xabs <= Base<R>::thr;
-  const bool mid = !common && xabs <= Base<R>::thrM;
-  const bool rare = !(xabs <= Base<R>::thrM);
+  // max|x| <= thrM < 1 implies max x <= 1, i.e. alpha_* = 2.  A lane in the
+  // rare phase was deferred by the common phase and stays rare: max|x_i|
+  // formed again by the loop accessors may round differently and must not
+  // send it back to a tier whose sums it has not formed.
+  const bool common = PHASE != kPhaseRare && xabs <= Base<R>::thr;
+  const bool mid = PHASE != kPhaseRare && !common && xabs <= Base<R>::thrM;
+  const bool rare = PHASE == kPhaseRare || !(xabs <= Base<R>::thrM);
   if constexpr (PHASE == kPhaseCommon) {
     if (rare) {
       o.deferred = true;
@@ -1561,7 +1564,7 @@ template <int D, class S, int MODE, class R, bool SUMS>
 __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const BatchArgs args) {
   using T = typename S::T;
   constexpr int Q = Lattice<D>::Q;
-  constexpr int ELBM_TILES = tiles_per_block(sizeof(T));
+  constexpr int ELBM_TILES = tiles_per_block(sizeof(T), Q);
   const int b = blockIdx.x;
   int si = 0;
   for (int k = 1; k < args.n; ++k)

@@ -359,7 +359,7 @@ template <class S, int MODE, class R, bool SUMS>
 __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step_q19(const BatchArgs args) {
   using T = typename S::T;
   constexpr int Q = 19;
-  constexpr int ELBM_TILES = tiles_per_block(sizeof(T));
+  constexpr int ELBM_TILES = tiles_per_block(sizeof(T), Q);
   const int b = blockIdx.x;
   int si = 0;
   for (int k = 1; k < args.n; ++k)

@@ -221,7 +221,7 @@ SHORT = [(2, (64, 64, 1), 60, dict(storage="f32", beta=0.99)),
          (3, (16, 12, 9), 40, dict(storage="f32dev", beta=0.98)),
          (19, (14, 10, 9), 60, dict(storage="f32", beta=0.98))]
 # for a pool with room for LONG only: each needs more than LONG's state leaves
-SHORT_POOL = [(2, (96, 96, 1), 60, dict(storage="f32", beta=0.99)),
+SHORT_POOL = [(2, (88, 88, 1), 60, dict(storage="f32", beta=0.99)),
               (3, (16, 12, 9), 40, dict(storage="f32dev", beta=0.98)),
               (2, (80, 96, 1), 60, dict(storage="f32", beta=0.99))]
 

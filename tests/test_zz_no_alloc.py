@@ -62,19 +62,22 @@ def test_step_noalloc_matches_step_and_stats(gpu):
 
 
 def test_step_noalloc_rejects_boxes_beyond_the_scratch(gpu):
-    """A box of more than 65536 workgroup records (2^24 sites) is refused
-    with ELBM_EINVAL before any launch; the limit itself is accepted."""
+    """A box of more than 65536 workgroup records is refused with
+    ELBM_EINVAL before any launch; the limit itself is accepted.  D3Q27
+    workgroups hold 256 sites, so the limit is 2^24 sites (256^3)."""
     dev_stats = torch.zeros(gpu.STATS_BYTES, dtype=torch.uint8, device="cuda")
-    n = 4100  # 4100^2 sites need 65664 records
-    rho, u = np.ones(n * n), np.zeros((2, n * n))
-    with gpu.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f16dev") as s:
-        with pytest.raises(gpu.ElbmError) as e:
-            s.step_noalloc(1, gpu.DIAG_COUNTS, dev_stats)
-        assert "scratch" in str(e.value) and s.t == 0
-    n = 4096  # exactly 65536 records
-    rho, u = np.ones(n * n), np.zeros((2, n * n))
-    with gpu.Simulation("d2q9", n, n, 1, rho0=rho, u0=u, storage="f16dev") as s:
-        s.step_noalloc(1, gpu.DIAG_COUNTS, dev_stats)
-        st = gpu.stats_from_bytes(dev_stats.cpu().numpy().tobytes())
-        assert st["n_sites"] == n * n and st["step"] == 1
-        assert st["n_accept2"] == n * n  # f = f^eq everywhere: the guard accepts alpha = 2
+    n = 256
+    for nz, ok in ((n + 1, False), (n, True)):
+        N = n * n * nz
+        rho, u = np.ones(N), np.zeros((3, N))
+        with gpu.Simulation("d3q27", n, n, nz, rho0=rho, u0=u, storage="f16dev") as s:
+            if not ok:
+                with pytest.raises(gpu.ElbmError) as e:
+                    s.step_noalloc(1, gpu.DIAG_COUNTS, dev_stats)
+                assert "scratch" in str(e.value) and s.t == 0
+            else:
+                s.step_noalloc(1, gpu.DIAG_COUNTS, dev_stats)
+                st = gpu.stats_from_bytes(dev_stats.cpu().numpy().tobytes())
+                assert st["n_sites"] == N and st["step"] == 1
+                # f = f^eq everywhere: the guard accepts alpha = 2
+                assert st["n_accept2"] == N
