@@ -390,8 +390,16 @@ struct SiteDev {
   typename Kept<S>::type raw[Q];
   float r, dr, rho32;  // rho_ref, rho - rho_ref, rho
   double rho, u[3];    // rho and u widened (alpha's guard, diagnostics)
-  float dxy[3][3];     // (1 + dl_x(dx)) (1 + dl_y(dy)) - 1
+  // s^eq_i = dr + rho Dl_i with Dl_i = (1 + a)(1 + dl_z(dz)) - 1,
+  // a = (1 + dl_x(dx)) (1 + dl_y(dy)) - 1, formed as one multiply-add
+  // s^eq_i = seqA + seqB dl_z(dz) from seqA = dr + rho a and seqB = rho (1 + a)
+  float seqA[3][3], seqB[3][3];
   float dlz[3];        // dl_z(dz)
+  // 1 / (rho_ref + s^eq_i) = W_i / f^eq_i = rxy[dx][dy] rlz[dz]: with
+  // rho_ref + s^eq_i = rho prod_a (1 + dl_a), the reciprocals of the nine
+  // per-axis factors (and 1/rho) give it with one product per direction
+  float rxy[3][3];     // 1 / (rho (1 + dl_x(dx)) (1 + dl_y(dy)))
+  float rlz[3];        // 1 / (1 + dl_z(dz))
   const T* src;
   uint32_t site;
   const SimDesc* desc;
@@ -403,12 +411,15 @@ struct SiteDev {
     else return fmaf(raw[i], float(L::invW(i)), -r);
   }
   struct Pass {
-    float dlz[3];
+    float dlz[3], rlz[3];
   };
   __device__ __forceinline__ Pass pass() const {
     Pass p;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) p.dlz[k] = dlz[k];
+    for (int k = 0; k < 3; ++k) {
+      p.dlz[k] = dlz[k];
+      p.rlz[k] = rlz[k];
+    }
     return p;
   }
   // copies hidden from the optimiser, so that the s^eq_i of different
@@ -416,22 +427,26 @@ struct SiteDev {
   __device__ __forceinline__ Pass pass_opaque() const {
     Pass p;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) p.dlz[k] = opaque(dlz[k]);
+    for (int k = 0; k < 3; ++k) {
+      p.dlz[k] = opaque(dlz[k]);
+      p.rlz[k] = opaque(rlz[k]);
+    }
     return p;
   }
   __device__ __forceinline__ float seq(int i, const Pass& p) const {
-    const float a = dxy[L::dg(i, 0)][L::dg(i, 1)];
-    const float b = p.dlz[L::dg(i, 2)];
-    return fmaf(rho32, D > 2 ? fmaf(a, b, a + b) : a, dr);
+    const float A = seqA[L::dg(i, 0)][L::dg(i, 1)];
+    return D > 2 ? fmaf(seqB[L::dg(i, 0)][L::dg(i, 1)], p.dlz[L::dg(i, 2)], A) : A;
   }
   __device__ __forceinline__ double fe(int i, const Pass& p) const {
     return double(float(L::W(i)) * (r + seq(i, p)));
   }
-  // x_i to FP32 relative accuracy (the reciprocal is the hardware one, 1 ulp):
-  // its absolute error is that of s_i - s^eq_i, O(|u|) times FP32 rounding
+  // x_i = (s_i - s^eq_i) / (rho_ref + s^eq_i) to FP32 relative accuracy
+  // (a few roundings of the reciprocal factors): its absolute error is that
+  // of s_i - s^eq_i, O(|u|) times FP32 rounding
   __device__ __forceinline__ double x(int i, const Pass& p) const {
     const float q = seq(i, p);
-    return double((s(i) - q) * __builtin_amdgcn_rcpf(r + q));
+    const float R = rxy[L::dg(i, 0)][L::dg(i, 1)];
+    return double((s(i) - q) * (D > 2 ? R * p.rlz[L::dg(i, 2)] : R));
   }
   // the stored value of s~_i.  FP32 storage holds f~_i = W_i (rho_ref + s~_i),
   // rounded once from W_i = wh + wl (wl: the residual of W_i's FP32
@@ -484,8 +499,8 @@ struct SiteDev {
     if constexpr (S::dev) si = float(gv);
     else si = fmaf(float(gv), invweight_of(i), -r);
     // the selections multiply by 0 and 1 and add zeros: exact
-    const float a = sel9(dxy, dx, dy), b = sel3(dlz, dz);
-    seqi = fmaf(rho32, D > 2 ? fmaf(a, b, a + b) : a, dr);
+    const float A = sel9(seqA, dx, dy);
+    seqi = D > 2 ? fmaf(sel9(seqB, dx, dy), sel3(dlz, dz), A) : A;
   }
   __device__ __forceinline__ void xfe(int i, double& xi, double& fi, double* = nullptr) const {
     float si, seqi;
@@ -726,10 +741,20 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // The rolled passes (rare tier, root solvers) re-read the populations
   // from the source buffer; their source offsets (v.w) are formed just
   // before each such pass rather than kept live through the whole update.
-  // Common tier: x_i, max|x_i| and the K-term series sums in one pass.
+  // Common tier: x_i, max|x_i| and the KC-term series sums in one pass.
+  // With 2-byte storage the stored result carries 11 bits: one term
+  // (E = sum f^eq x^2 / 2, O = sum f^eq x^3 / 6) up to max|x_i| <= thrM =
+  // 0.025 leaves out x^4/12 of E and x^5/20 of O, which moves 2 - alpha
+  // (<= 2|x|/3) by at most 0.47 x^2 of itself, alpha by at most 5e-6 and
+  // f~_i = f^eq_i (1 + (1 - alpha beta) x_i) by at most 1.3e-7 f^eq_i: about
+  // 2 % of half a unit of an FP16 deviation s_i of the size of x_i.  With 4-
+  // and 8-byte storage the tiers keep alpha to 2^-53.
+  constexpr bool kS16 = sizeof(typename V::T) == 2 && std::is_same<R, double>::value;
+  constexpr int KC = kS16 ? 1 : Base<R>::K;
+  const R thrC = kS16 ? Base<R>::thrM : Base<R>::thr;
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   if constexpr (PHASE != kPhaseRare) {
-  const SeriesK<R, Base<R>::K> ser;
+  const SeriesK<R, KC> ser;
   const auto P = v.pass();
   if constexpr (V::kZFactor) {
     // f^eq_i = f01[dx][dy] e2[dz]: the sums over dz are formed with e2
@@ -762,7 +787,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   }
   if constexpr (PHASE != kPhaseRare) {
     R cE, cO;
-    series_scale<R, Base<R>::K>(cE, cO);
+    series_scale<R, KC>(cE, cO);
     sE *= cE;
     sO *= cO;
   } else {
@@ -782,7 +807,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // rare phase was deferred by the common phase and stays rare: max|x_i|
   // formed again by the loop accessors may round differently and must not
   // send it back to a tier whose sums it has not formed.
-  const bool common = PHASE != kPhaseRare && xabs <= Base<R>::thr;
+  const bool common = PHASE != kPhaseRare && xabs <= thrC;
   const bool mid = PHASE != kPhaseRare && !common && xabs <= Base<R>::thrM;
   const bool rare = PHASE == kPhaseRare || !(xabs <= Base<R>::thrM);
   if constexpr (PHASE == kPhaseCommon) {
@@ -985,15 +1010,34 @@ __device__ __forceinline__ int wsumi(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
+// Wavefront min / max of a float by data-parallel-primitive moves (one VALU
+// operation per step instead of an LDS permute and its lane arithmetic):
+// lane pairs and quads (quad_perm [1,0,3,2], [2,3,0,1]), half rows and rows
+// of 16 lanes (row_half_mirror, row_mirror; every lane then holds its row's
+// result), row 0 into row 1 and row 2 into row 3 (row_bcast:15 on rows 1 and
+// 3), rows 0-1 into rows 2-3 (row_bcast:31 on rows 2 and 3); lane 63 holds
+// the wavefront's result.  All lanes must be active; min and max are exact,
+// so the result does not depend on the order.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+      __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+}
+template <class OP>
+__device__ __forceinline__ float wreduce_dpp(float v, OP op) {
+  v = op(v, dpp_f32<0xB1>(v));        // quad_perm [1,0,3,2]
+  v = op(v, dpp_f32<0x4E>(v));        // quad_perm [2,3,0,1]
+  v = op(v, dpp_f32<0x141>(v));       // row_half_mirror
+  v = op(v, dpp_f32<0x140>(v));       // row_mirror
+  v = op(v, dpp_f32<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_f32<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
 __device__ __forceinline__ float wminf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-  return v;
+  return wreduce_dpp(v, [](float a, float b) { return fminf(a, b); });
 }
 __device__ __forceinline__ float wmaxf(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  return wreduce_dpp(v, [](float a, float b) { return fmaxf(a, b); });
 }
 
 // Wavefront reductions, then a fixed-order combination over the block's
@@ -1229,13 +1273,17 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
       },
       dr, j32);
   const float rho32 = v.r + dr;
-  const float irho = rcp_n<float>(rho32);
+  // FP32 arithmetic: the hardware reciprocal refined by one Newton step
+  // (e = 1 - rho r, r <- r + r e) and the hardware square root (1 ulp)
+  // instead of the correctly rounded library division and square root
+  const float irho0 = __builtin_amdgcn_rcpf(rho32);
+  const float irho = fmaf(irho0, fmaf(-rho32, irho0, 1.0f), irho0);
   float dl[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
       const float ua = j32[a] * irho, t = 3.0f * ua * ua;
-      const float q = t * __builtin_amdgcn_rcpf(1.0f + sqrt_n<float>(1.0f + t));
+      const float q = t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + t));
       dl[a][0] = -q;
       dl[a][1] = fmaf(3.0f, ua, 2.0f * q);
       dl[a][2] = fmaf(-3.0f, ua, 2.0f * q);
@@ -1245,13 +1293,25 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
       v.u[a] = 0.0;
     }
   }
+  float rl[3][3];  // 1 / (1 + dl_a(d)), the hardware reciprocal (1 ulp)
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
-      v.dxy[a][b] = D > 1 ? fmaf(dl[0][a], dl[1][b], dl[0][a] + dl[1][b]) : dl[0][a];
+    for (int b = 0; b < 3; ++b) rl[a][b] = a < D ? __builtin_amdgcn_rcpf(1.0f + dl[a][b]) : 1.0f;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) v.dlz[k] = dl[2][k];
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float dxy = D > 1 ? fmaf(dl[0][a], dl[1][b], dl[0][a] + dl[1][b]) : dl[0][a];
+      v.seqA[a][b] = fmaf(rho32, dxy, dr);
+      v.seqB[a][b] = fmaf(rho32, dxy, rho32);
+      v.rxy[a][b] = D > 1 ? irho * rl[0][a] * rl[1][b] : irho * rl[0][a];
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v.dlz[k] = dl[2][k];
+    v.rlz[k] = rl[2][k];
+  }
   v.dr = dr;
   v.rho32 = rho32;
   v.rho = rho32;
@@ -1545,17 +1605,24 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
 // the cache lines at their x-edges, then run on the same XCD and L2.  Each
 // simulation's workgroup count is a multiple of 8 and starts at a multiple
 // of 8.
-// Waves per SIMD the step kernel is compiled for: four (at most 128 vector
-// registers) for the closed form and LBGK on 2- and 4-byte storage, whose
-// common path fits in that budget, so that four waves per SIMD hide the
-// memory latency; the root solvers and FP64 storage keep the registers
-// they need.
+// The root solvers and FP64 storage keep the registers they need (Newton
+// with 2- and 4-byte storage: three waves per SIMD).
 #ifndef ELBM_NEWTON_WAVES
 #define ELBM_NEWTON_WAVES 3
 #endif
+#ifndef ELBM_CLOSED_WAVES
+#define ELBM_CLOSED_WAVES 4
+#endif
+// Waves per SIMD the step kernel is compiled for.  Closed form and LBGK on
+// 4-byte storage: four (at most 128 VGPRs; the common path has no spills).
+// Closed form on 2-byte storage: three (its common path holds about 140
+// VGPRs: the decoded deviations and the per-axis factors of both the
+// equilibrium and its reciprocal; four waves spill in the common path and
+// run 5.02 ms against 3.86 ms at 512^3 with mixed arithmetic).
 template <class S, int MODE>
 constexpr int step_waves() {
-  if (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) return 4;
+  if (sizeof(typename S::T) == 2 && MODE == kClosed) return 3;
+  if (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) return ELBM_CLOSED_WAVES;
   if (sizeof(typename S::T) <= 4 && MODE == kNewton) return ELBM_NEWTON_WAVES;
   return 1;
 }
