@@ -242,6 +242,7 @@ struct Site {
   static constexpr int kDim = D;
   // f^eq_i = f01[dx][dy] e2[dz]: the common tier sums over c_z per (c_x, c_y)
   static constexpr bool kZFactor = (D == 3);
+  static constexpr bool kSumsK1 = false;
   typename Kept<S>::type raw[Q];  // the loaded populations as kept (Kept<S>)
   R rho, irho, rho_ref;
   R u[3];
@@ -387,6 +388,7 @@ struct SiteDev {
   static constexpr int Q = L::Q;
   static constexpr int kDim = D;
   static constexpr bool kZFactor = false;  // f^eq_i comes from s^eq_i
+  static constexpr bool kSumsK1 = true;     // sums_k1() below
   typename Kept<S>::type raw[Q];
   float r, dr, rho32;  // rho_ref, rho - rho_ref, rho
   double rho, u[3];    // rho and u widened (alpha's guard, diagnostics)
@@ -443,10 +445,46 @@ struct SiteDev {
   // x_i = (s_i - s^eq_i) / (rho_ref + s^eq_i) to FP32 relative accuracy
   // (a few roundings of the reciprocal factors): its absolute error is that
   // of s_i - s^eq_i, O(|u|) times FP32 rounding
-  __device__ __forceinline__ double x(int i, const Pass& p) const {
-    const float q = seq(i, p);
+  __device__ __forceinline__ float rfac(int i, const Pass& p) const {
     const float R = rxy[L::dg(i, 0)][L::dg(i, 1)];
-    return double((s(i) - q) * (D > 2 ? R * p.rlz[L::dg(i, 2)] : R));
+    return D > 2 ? R * p.rlz[L::dg(i, 2)] : R;
+  }
+  __device__ __forceinline__ double x(int i, const Pass& p) const {
+    return double((s(i) - seq(i, p)) * rfac(i, p));
+  }
+  // The common-tier sums to their first terms, E = sum_i f^eq_i x_i^2 / 2
+  // and O = sum_i f^eq_i x_i^3 / 6, in FP32, and max_i |x_i|: for results
+  // stored in 2 bytes (the FP32 rounding moves alpha by about 2^-24 max|x_i|,
+  // far below what 11 stored bits resolve).  With d_i = s_i - s^eq_i,
+  // f^eq_i x_i = W_i d_i, so E and O are W-weighted sums of d_i x_i and
+  // d_i x_i^2, summed per weight class (W_i = 4^z / 6^D, z the number of
+  // zero components of c_i) and weighted once at the end.
+  __device__ __forceinline__ void sums_k1(const Pass& p, double& sE, double& sO,
+                                          double& xabs) const {
+    float e[D + 1], o[D + 1], xm = 0.0f;
+#pragma unroll
+    for (int z = 0; z <= D; ++z) e[z] = o[z] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float di = s(i) - seq(i, p);
+      const float xi = di * rfac(i, p);
+      const float t = di * xi;
+      const int z = L::nzero(i);
+      e[z] += t;
+      o[z] = fmaf(t, xi, o[z]);
+      xm = fmaxf(xm, fabsf(xi));
+      sched_group(i);
+    }
+    double E = 0.0, O = 0.0;
+#pragma unroll
+    for (int z = 0; z <= D; ++z) {
+      const double wz = double(1 << (2 * z)) / L::den();
+      E = fma(wz, double(e[z]), E);
+      O = fma(wz, double(o[z]), O);
+    }
+    sE = 0.5 * E;
+    sO = O * (1.0 / 6.0);
+    xabs = double(xm);
   }
   // the stored value of s~_i.  FP32 storage holds f~_i = W_i (rho_ref + s~_i),
   // rounded once from W_i = wh + wl (wl: the residual of W_i's FP32
@@ -753,7 +791,10 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   constexpr int KC = kS16 ? 1 : Base<R>::K;
   const R thrC = kS16 ? Base<R>::thrM : Base<R>::thr;
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
-  if constexpr (PHASE != kPhaseRare) {
+  constexpr bool kK1 = kS16 && V::kSumsK1 && !kXmax;
+  if constexpr (PHASE != kPhaseRare && kK1) {
+    v.sums_k1(v.pass(), sE, sO, xabs);
+  } else if constexpr (PHASE != kPhaseRare) {
   const SeriesK<R, KC> ser;
   const auto P = v.pass();
   if constexpr (V::kZFactor) {
@@ -786,10 +827,12 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   }
   }
   if constexpr (PHASE != kPhaseRare) {
-    R cE, cO;
-    series_scale<R, KC>(cE, cO);
-    sE *= cE;
-    sO *= cO;
+    if constexpr (!kK1) {
+      R cE, cO;
+      series_scale<R, KC>(cE, cO);
+      sE *= cE;
+      sO *= cO;
+    }
   } else {
     // only deferred lanes are active: max|x_i| again, by the loop accessors
     v.w = locate<D>(d, v.site);

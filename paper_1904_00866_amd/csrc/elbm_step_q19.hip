@@ -46,6 +46,7 @@ struct SiteQ19 {
   static constexpr int Q = 19;
   static constexpr int kDim = 3;
   static constexpr bool kZFactor = false;
+  static constexpr bool kSumsK1 = false;
   typename Kept<S>::type raw[Q];  // the loaded populations as kept (Kept<S>)
   R rho, irho, rho_ref;
   R u[3];
