@@ -164,6 +164,24 @@ __device__ __forceinline__ T ld_buf(__amdgpu_buffer_rsrc_t r, uint32_t boff, uin
   }
 }
 
+// A loaded population as the loaders hand it to the site update: 2-byte
+// values are held zero-extended, one per 32-bit register.  Kept as 16-bit
+// values, they are packed two to a register as soon as they arrive, so the
+// wavefront waits for each group of loads before it issues the next and the
+// loads of several tiles are no longer in flight together.
+template <class T>
+using Slot = typename std::conditional<sizeof(T) == 2, uint32_t, T>::type;
+template <class T>
+__device__ __forceinline__ Slot<T> ld_slot(__amdgpu_buffer_rsrc_t r, uint32_t boff, uint32_t soff) {
+  if constexpr (sizeof(T) == 2) return uint32_t(__builtin_amdgcn_raw_buffer_load_b16(r, boff, soff, 0));
+  else return ld_buf<T>(r, boff, soff);
+}
+template <class T>
+__device__ __forceinline__ T from_slot(Slot<T> v) {
+  if constexpr (sizeof(T) == 2) return __builtin_bit_cast(T, uint16_t(v));
+  else return v;
+}
+
 // Non-temporal store of one population into a range of `bytes` bytes at
 // `base`, as a raw buffer store: the descriptor is formed in scalar
 // registers and the lane's byte offset is the only vector operand, so a
@@ -459,8 +477,7 @@ struct SiteDev {
   // f^eq_i x_i = W_i d_i, so E and O are W-weighted sums of d_i x_i and
   // d_i x_i^2, summed per weight class (W_i = 4^z / 6^D, z the number of
   // zero components of c_i) and weighted once at the end.
-  __device__ __forceinline__ void sums_k1(const Pass& p, double& sE, double& sO,
-                                          double& xabs) const {
+  __device__ __forceinline__ void sums_k1(const Pass& p, float& sE, float& sO, float& xabs) const {
     float e[D + 1], o[D + 1], xm = 0.0f;
 #pragma unroll
     for (int z = 0; z <= D; ++z) e[z] = o[z] = 0.0f;
@@ -475,16 +492,16 @@ struct SiteDev {
       xm = fmaxf(xm, fabsf(xi));
       sched_group(i);
     }
-    double E = 0.0, O = 0.0;
+    float E = 0.0f, O = 0.0f;
 #pragma unroll
     for (int z = 0; z <= D; ++z) {
-      const double wz = double(1 << (2 * z)) / L::den();
-      E = fma(wz, double(e[z]), E);
-      O = fma(wz, double(o[z]), O);
+      const float wz = float(double(1 << (2 * z)) / L::den());
+      E = fmaf(wz, e[z], E);
+      O = fmaf(wz, o[z], O);
     }
-    sE = 0.5 * E;
-    sO = O * (1.0 / 6.0);
-    xabs = double(xm);
+    sE = 0.5f * E;
+    sO = O * float(1.0 / 6.0);
+    xabs = xm;
   }
   // the stored value of s~_i.  FP32 storage holds f~_i = W_i (rho_ref + s~_i),
   // rounded once from W_i = wh + wl (wl: the residual of W_i's FP32
@@ -776,6 +793,39 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // The root solvers need alpha_max on every lane; the closed form and the
   // secant need it only where alpha_* < 2, which the tiers below detect.
   constexpr bool kXmax = (MODE == kNewton || MODE == kBisect);
+  // 2-byte storage: the first-term sums in FP32 (sums_k1)
+  constexpr bool kS16 = sizeof(typename V::T) == 2 && std::is_same<R, double>::value;
+  constexpr bool kK1 = kS16 && V::kSumsK1 && !kXmax;
+  if constexpr (kK1 && MODE == kClosed && PHASE == kPhaseCommon) {
+    // The common phase of the closed form on them, in FP32: alpha_* = 2
+    // (max|x_i| <= 0.025 < 1), D = E - O, G(2) = 2 O, D*(2) = E + O, and
+    // Eq. (9) gives alpha = 2 - 2 O / (E + O) where G(2) > 0.  The quotient
+    // (below |x| / 3) carries FP32 rounding; 2 minus it is formed in FP64.
+    float E, O, xm;
+    v.sums_k1(v.pass(), E, O, xm);
+    o.iters = 0;
+    o.astar_lt2 = o.fallback = false;
+    if (!(xm <= float(Base<R>::thrM))) {
+      o.deferred = true;
+      o.alpha = R(2);
+      o.D = R(0);
+      o.accepted2 = o.guard = false;
+      return o;
+    }
+    const float Dv = E - O;
+    o.D = R(Dv);
+    o.guard = !(R(Dv) > Prec<R>::guard * v.rho);
+    o.accepted2 = o.guard || !(O > 0.0f);
+    o.alpha = R(2);
+    if (!o.accepted2) {
+      const float Ds = E + O;
+      const float r0 = __builtin_amdgcn_rcpf(Ds);
+      const float r = fmaf(r0, fmaf(-Ds, r0, 1.0f), r0);
+      o.alpha = fmax(R(2) - R(2.0f * O * r), R(1));
+      o.iters = 1;
+    }
+    return o;
+  }
   // The rolled passes (rare tier, root solvers) re-read the populations
   // from the source buffer; their source offsets (v.w) are formed just
   // before each such pass rather than kept live through the whole update.
@@ -787,13 +837,15 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // f~_i = f^eq_i (1 + (1 - alpha beta) x_i) by at most 1.3e-7 f^eq_i: about
   // 2 % of half a unit of an FP16 deviation s_i of the size of x_i.  With 4-
   // and 8-byte storage the tiers keep alpha to 2^-53.
-  constexpr bool kS16 = sizeof(typename V::T) == 2 && std::is_same<R, double>::value;
   constexpr int KC = kS16 ? 1 : Base<R>::K;
   const R thrC = kS16 ? Base<R>::thrM : Base<R>::thr;
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
-  constexpr bool kK1 = kS16 && V::kSumsK1 && !kXmax;
   if constexpr (PHASE != kPhaseRare && kK1) {
-    v.sums_k1(v.pass(), sE, sO, xabs);
+    float E, O, xm;
+    v.sums_k1(v.pass(), E, O, xm);
+    sE = E;
+    sO = O;
+    xabs = xm;
   } else if constexpr (PHASE != kPhaseRare) {
   const SeriesK<R, KC> ser;
   const auto P = v.pass();
@@ -1155,7 +1207,7 @@ __device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
 // (x, x - 1, x + 1 with periodic wrap) are per-lane offsets.
 template <int D, class T>
 __device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, uint32_t s,
-                                              T (&raw)[Lattice<D>::Q]) {
+                                              Slot<T> (&raw)[Lattice<D>::Q]) {
   using L = Lattice<D>;
   const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
   // row index of the wavefront (uniform), x per lane
@@ -1198,7 +1250,7 @@ __device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, ui
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
         const int i = dx + 3 * dy + 9 * dz;
-        raw[i] = ld_buf<T>(r, xo[dx], (uint32_t)i * kLane * es);
+        raw[i] = ld_slot<T>(r, xo[dx], (uint32_t)i * kLane * es);
       }
     }
 }
@@ -1206,14 +1258,15 @@ __device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, ui
 // Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
 template <int D, class T>
 __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32_t s,
-                                          T (&raw)[Lattice<D>::Q]) {
+                                          Slot<T> (&raw)[Lattice<D>::Q]) {
   using L = Lattice<D>;
   const Where w = locate<D>(d, s);
   const gaddr base = buffer_base(src);
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const uint32_t sp = w.zs[L::dg(i, 2)] + w.ys[L::dg(i, 1)] + w.xs[L::dg(i, 0)];
-    raw[i] = *(const gptr<T>)(base + pidx<L::Q>(sp, i) * sizeof(T));
+    using U = typename std::conditional<sizeof(T) == 2, uint16_t, T>::type;
+    raw[i] = Slot<T>(*(const gptr<U>)(base + pidx<L::Q>(sp, i) * sizeof(T)));
   }
 }
 
@@ -1336,24 +1389,42 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
       v.u[a] = 0.0;
     }
   }
-  float rl[3][3];  // 1 / (1 + dl_a(d)), the hardware reciprocal (1 ulp)
+  // 1 / (1 + dl_a(c)) from one reciprocal: with F_c = 1 + dl_a(c), the
+  // cofactor C_c (product of the other two factors of the axis) and
+  // P_a = F_0 F_+ F_- = F_c C_c, 1 / F_c = C_c / P_a.  The x and y axes share
+  // one reciprocal, 1 / (rho P_x P_y), times 1/rho's; z has its own.  Each
+  // quotient carries a few FP32 roundings (the hardware reciprocal is good to
+  // 1 ulp).
+  float C[3][3], P[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) {
+      const float F0 = 1.0f + dl[a][0], Fp = 1.0f + dl[a][1], Fm = 1.0f + dl[a][2];
+      C[a][0] = Fp * Fm;
+      C[a][1] = F0 * Fm;
+      C[a][2] = F0 * Fp;
+      P[a] = F0 * C[a][0];
+    } else {
+      C[a][0] = C[a][1] = C[a][2] = P[a] = 1.0f;
+    }
+  }
+  const float Rxy = irho * __builtin_amdgcn_rcpf(D > 1 ? P[0] * P[1] : P[0]);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) rl[a][b] = a < D ? __builtin_amdgcn_rcpf(1.0f + dl[a][b]) : 1.0f;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 3; ++a) {
+    const float Rx = Rxy * C[0][a];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       const float dxy = D > 1 ? fmaf(dl[0][a], dl[1][b], dl[0][a] + dl[1][b]) : dl[0][a];
       v.seqA[a][b] = fmaf(rho32, dxy, dr);
       v.seqB[a][b] = fmaf(rho32, dxy, rho32);
-      v.rxy[a][b] = D > 1 ? irho * rl[0][a] * rl[1][b] : irho * rl[0][a];
+      v.rxy[a][b] = D > 1 ? Rx * C[1][b] : Rx;
     }
+  }
+  const float Rz = D > 2 ? __builtin_amdgcn_rcpf(P[2]) : 1.0f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     v.dlz[k] = dl[2][k];
-    v.rlz[k] = rl[2][k];
+    v.rlz[k] = Rz * C[2][k];
   }
   v.dr = dr;
   v.rho32 = rho32;
@@ -1412,7 +1483,7 @@ __device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
                                                 const typename S::T* __restrict__ src,
                                                 typename S::T* __restrict__ dst, uint32_t s,
                                                 bool live,
-                                                const typename S::T (&raw)[Lattice<D>::Q],
+                                                const Slot<typename S::T> (&raw)[Lattice<D>::Q],
                                                 Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
@@ -1421,7 +1492,7 @@ __device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
   const uint32_t sl = live ? s : 0u;
   SiteDev<D, S> v;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(from_slot<typename S::T>(raw[i]));
   double j[3];
   site_prepare_dev(v, d, src, sl, j);
   const AlphaOut<double> ao = choose_alpha<MODE, PHASE>(v, d);
@@ -1447,7 +1518,7 @@ template <int D, class S, int MODE, class R, bool SUMS, int PHASE>
 __device__ __forceinline__ SiteOut site_update_fp(const SimDesc& d,
                                                const typename S::T* __restrict__ src,
                                                typename S::T* __restrict__ dst, uint32_t s,
-                                               bool live, const typename S::T (&raw)[Lattice<D>::Q],
+                                               bool live, const Slot<typename S::T> (&raw)[Lattice<D>::Q],
                                                Acc& acc, int diag) {
   using L = Lattice<D>;
   constexpr int Q = L::Q;
@@ -1457,7 +1528,7 @@ __device__ __forceinline__ SiteOut site_update_fp(const SimDesc& d,
 
   Site<D, S, R> v;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
+  for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(from_slot<typename S::T>(raw[i]));
   R rho, j[3];
   site_prepare(v, d, src, sl, rho, j, MODE != kBGK);
   const R beta = (R)d.beta;
@@ -1535,7 +1606,7 @@ __device__ __forceinline__ SiteOut site_update_fp(const SimDesc& d,
 template <int D, class S, int MODE, class AP, bool SUMS, int PHASE = kPhaseAll>
 __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename S::T* __restrict__ src,
                                             typename S::T* __restrict__ dst, uint32_t s,
-                                            bool live, const typename S::T (&raw)[Lattice<D>::Q],
+                                            bool live, const Slot<typename S::T> (&raw)[Lattice<D>::Q],
                                             Acc& acc, int diag) {
   if constexpr (kIsMixed<AP>)
     return site_update_dev<D, S, MODE, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
@@ -1554,10 +1625,10 @@ __device__ __forceinline__ uint32_t site_update_rare_dev(const SimDesc& d, const
   const uint32_t sl = live ? s : 0u;
   SiteDev<D, S> v;
   if constexpr (Codec<S, double>::kF16) {
-    T raw[Q];
+    Slot<T> raw[Q];
     load_site<D>(d, src, sl, raw);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(raw[i]);
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(from_slot<T>(raw[i]));
   } else {
     load_site<D>(d, src, sl, v.raw);
   }
@@ -1595,10 +1666,10 @@ __device__ __forceinline__ uint32_t site_update_rare_fp(const SimDesc& d, const 
   const uint32_t sl = live ? s : 0u;
   Site<D, S, R> v;
   if constexpr (Codec<S, R>::kF16) {
-    T raw[Q];
+    Slot<T> raw[Q];
     load_site<D>(d, src, sl, raw);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(raw[i]);
+    for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, R>::keep(from_slot<T>(raw[i]));
   } else {
     load_site<D>(d, src, sl, v.raw);
   }
@@ -1690,17 +1761,26 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
   Acc acc;
   acc.init();
   if (unit * ELBM_TILES * kBlock < N) {
-    T raw[ELBM_TILES][Q];
+    Slot<T> raw[ELBM_TILES][Q];
 #if ELBM_LOAD_PRIO
     __builtin_amdgcn_s_setprio(ELBM_LOAD_PRIO);
 #endif
+    // the loads of every tile issued back to back, on one path (a branch per
+    // tile would put control-flow joins between them, at which the
+    // compiler's wait counting turns conservative)
+    const uint32_t s0 = unit * ELBM_TILES * kBlock + threadIdx.x;
+    if (d.nx % 64 == 0) {
 #pragma unroll
-    for (int k = 0; k < ELBM_TILES; ++k) {
-      const uint32_t s = (unit * ELBM_TILES + k) * kBlock + threadIdx.x;
-      if (d.nx % 64 == 0)
+      for (int k = 0; k < ELBM_TILES; ++k) {
+        const uint32_t s = s0 + k * kBlock;
         load_site_row<D>(d, src, s < N ? s : 0u, raw[k]);
-      else
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < ELBM_TILES; ++k) {
+        const uint32_t s = s0 + k * kBlock;
         load_site<D>(d, src, s < N ? s : 0u, raw[k]);
+      }
     }
 #if ELBM_LOAD_PRIO
     __builtin_amdgcn_sched_barrier(0);
