@@ -1255,6 +1255,69 @@ __device__ __forceinline__ void load_site_row(const SimDesc& d, const T* src, ui
     }
 }
 
+// The loads of a group of TILES tiles that lie in one x-row (nx a multiple of
+// TILES kBlock: the group is TILES kBlock consecutive sites of one row, tile
+// k's sites are tile 0's plus k kBlock, and their elements sit
+// k kBlock Q further on).  The per-lane offsets of tile 0 serve every tile,
+// with the tile's shift in the scalar offset; only tile 0's x - 1 and the
+// last tile's x + 1 can wrap around the row, and those two take offsets of
+// their own.  Every vector offset is a non-negative position inside the row.
+template <int D, int TILES, class T>
+__device__ __forceinline__ void load_group_row(const SimDesc& d, const T* src, uint32_t s0,
+                                               Slot<T> (&raw)[TILES][Lattice<D>::Q]) {
+  using L = Lattice<D>;
+  constexpr int Q = L::Q;
+  constexpr uint32_t es = sizeof(T);
+  const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny, nz = (uint32_t)d.nz;
+  const uint32_t row = __builtin_amdgcn_readfirstlane(D == 1 ? 0u : qdiv(s0, d.inv_nx));
+  const uint32_t x = s0 - row * nx;  // tile 0's x
+  uint32_t ys[3] = {0u, 0u, 0u}, zs[3] = {0u, 0u, 0u};
+  if constexpr (D > 1) {
+    const uint32_t z = D == 3 ? __builtin_amdgcn_readfirstlane(qdiv(row, d.inv_ny)) : 0u;
+    const uint32_t y = row - z * ny;
+    ys[0] = y * nx;
+    ys[1] = (y == 0 ? ny - 1 : y - 1) * nx;
+    ys[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+    const uint32_t nxy = nx * ny;
+    zs[0] = z * nxy;
+    zs[1] = (z == 0 ? nz - 1 : z - 1) * nxy;
+    zs[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+  }
+  constexpr uint32_t step = (uint32_t)kBlock * Q * es;  // bytes from one tile to the next
+  const auto off = [](uint32_t xx) { return (uint32_t)pidx<Q>(xx, 0) * es; };
+  const uint32_t o0 = off(x);
+  const uint32_t om0 = off(x == 0 ? nx - 1 : x - 1);   // tile 0, x - 1 (wrapped)
+  const uint32_t om1 = off(x + kBlock - 1);             // tile 1, x - 1
+  const uint32_t op = off(x + 1);                       // x + 1 of the tiles before the last
+  const uint32_t xl = x + (TILES - 1) * kBlock;         // the last tile's x
+  const uint32_t opl = xl == nx - 1 ? 0u : op + (TILES - 1) * step;  // its x + 1 (wrapped)
+  const gaddr base = buffer_base(src);
+  const uint32_t rowbytes = nx * (uint32_t)Q * es;
+  constexpr int NR = (D > 2 ? 3 : 1) * (D > 1 ? 3 : 1);  // source rows (c_y, c_z)
+  __amdgpu_buffer_rsrc_t r[NR];
+#pragma unroll
+  for (int n = 0; n < NR; ++n)
+    r[n] = rsrc(base + (uint64_t)(zs[n / 3] + ys[n % 3]) * Q * es, rowbytes);
+  // tile by tile, so that a tile's loads complete before the next tile's
+  // (a scheduling barrier per tile keeps the compiler from regrouping them
+  // by source row)
+#pragma unroll
+  for (int k = 0; k < TILES; ++k) {
+    if (k > 0) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      const int i0 = 3 * n;  // i = dx + 3 dy + 9 dz with n = dy + 3 dz
+      const uint32_t so = (uint32_t)i0 * kLane * es;
+      // c_x = 0, +1 (source x - 1), -1 (source x + 1)
+      raw[k][i0] = ld_slot<T>(r[n], o0, so + k * step);
+      raw[k][i0 + 1] = k == 0 ? ld_slot<T>(r[n], om0, so + kLane * es)
+                              : ld_slot<T>(r[n], om1, so + kLane * es + (k - 1) * step);
+      raw[k][i0 + 2] = k == TILES - 1 ? ld_slot<T>(r[n], opl, so + 2 * kLane * es)
+                                      : ld_slot<T>(r[n], op, so + 2 * kLane * es + k * step);
+    }
+  }
+}
+
 // Pull the Q populations of site s (s < N): raw_i = src_i(x - c_i).
 template <int D, class T>
 __device__ __forceinline__ void load_site(const SimDesc& d, const T* src, uint32_t s,
@@ -1769,7 +1832,10 @@ __global__ void __launch_bounds__(kBlock, (step_waves<S, MODE>())) k_step(const 
     // tile would put control-flow joins between them, at which the
     // compiler's wait counting turns conservative)
     const uint32_t s0 = unit * ELBM_TILES * kBlock + threadIdx.x;
-    if (d.nx % 64 == 0) {
+    if (ELBM_TILES > 1 && d.nx % (ELBM_TILES * kBlock) == 0) {
+      // (then N is a multiple of the group: every site is live)
+      load_group_row<D, ELBM_TILES>(d, src, s0, raw);
+    } else if (d.nx % 64 == 0) {
 #pragma unroll
       for (int k = 0; k < ELBM_TILES; ++k) {
         const uint32_t s = s0 + k * kBlock;

@@ -295,6 +295,41 @@ def test_one_step_row_aligned_boxes(gpu, orc, D, storage, mode):
     sim.close()
 
 
+# x-rows of whole groups of four 256-site tiles (nx a multiple of 1024): one
+# group per row, two per row, and D1Q3 with two groups
+GROUP_SHAPES = [(2048, 1, 1), (1024, 3, 1), (2048, 2, 1)]
+
+
+@pytest.mark.parametrize("shape", GROUP_SHAPES)
+@pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
+@pytest.mark.parametrize("mode", ["closed", "bgk"])
+def test_one_step_row_group_boxes(gpu, orc, shape, storage, mode):
+    """With 4- and 2-byte storage the D1Q3 and D2Q9 kernels update four
+    tiles per workgroup; when the x-rows hold whole groups of them, the loads
+    of every tile take the first tile's offsets shifted by a scalar, and only
+    the first tile's x - 1 and the last tile's x + 1 wrap around the row.
+    One step against the oracle from the decoded stored state, to one output
+    rounding, on every site (both wraps included)."""
+    D = 1 if shape[1] == 1 else 2
+    N = int(np.prod(shape))
+    f0 = _random_state(D, N, seed=760 + 10 * D + len(storage) + len(mode) + shape[1],
+                       eps=0.02, tilt=0.05)
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.97, mode=mode)
+    fq = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    fo, _, _ = orc.step(_ocfg(orc, D, shape, beta=0.97, mode=mode), fq)
+    W = H.textbook_weights(D)[:, None]
+    if storage == "f32":
+        tol = 2.0 ** -24 * np.abs(fo) * 1.01 + 1e-300
+    elif storage == "f32dev":
+        tol = W * (2.0 ** -24 * np.abs(fo / W - 1.0) * 1.01 + 1e-12)
+    else:
+        tol = W * (2.0 ** -11 * np.abs(fo / W - 1.0) * 1.01 + 2.0 ** -24)
+    assert np.all(np.abs(fg - fo) <= tol)
+    sim.close()
+
+
 def test_fp32_arithmetic_ablation(gpu, orc):
     """All-FP32 site arithmetic (closed form): one step within 2e-6 relative."""
     shape = SHAPES[2]
