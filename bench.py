@@ -277,10 +277,10 @@ def main() -> int:
                     help="requests of the Poisson serving stream (0: skip serving)")
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-steady-requests", type=int, default=120)
-    ap.add_argument("--serving-steady-rate", type=float, default=5.5,
+    ap.add_argument("--serving-steady-rate", type=float, default=6.2,
                     help="arrival rate of the second stream: its 120 requests (seed "
-                         "20250102) average 8.5e9 site updates, so 5.5/s offers 4.7e10 "
-                         "site updates per second, about 0.7 of the 6.6e10 the overloaded "
+                         "20250102) average 8.5e9 site updates, so 6.2/s offers 5.3e10 "
+                         "site updates per second, about 0.7 of the 7.5e10 the overloaded "
                          "stream reaches")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (a known-size kernel "
