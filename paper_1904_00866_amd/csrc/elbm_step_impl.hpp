@@ -1082,7 +1082,7 @@ struct Acc {
     for (int k = 0; k < kNumCounts; ++k) c[k] = 0;
     iters = 0;
     amin = INFINITY;
-    amax = -INFINITY;
+    amax = 0.0f;  // alpha >= 1: +0 is below every value (see wmax_nonneg)
     rho = j[0] = j[1] = j[2] = H = 0.0;
   }
   // wavefront counts of the count predicates; all lanes must be active
@@ -1105,34 +1105,42 @@ __device__ __forceinline__ int wsumi(int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
-// Wavefront min / max of a float by data-parallel-primitive moves (one VALU
-// operation per step instead of an LDS permute and its lane arithmetic):
-// lane pairs and quads (quad_perm [1,0,3,2], [2,3,0,1]), half rows and rows
-// of 16 lanes (row_half_mirror, row_mirror; every lane then holds its row's
-// result), row 0 into row 1 and row 2 into row 3 (row_bcast:15 on rows 1 and
-// 3), rows 0-1 into rows 2-3 (row_bcast:31 on rows 2 and 3); lane 63 holds
-// the wavefront's result.  All lanes must be active; min and max are exact,
-// so the result does not depend on the order.
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ float dpp_f32(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-      __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+// Wavefront min / max by data-parallel-primitive moves (one VALU operation
+// per step instead of an LDS permute and its lane arithmetic): lane pairs
+// and quads (quad_perm [1,0,3,2], [2,3,0,1]), half rows and rows of 16 lanes
+// (row_half_mirror, row_mirror; every lane then holds its row's result), row
+// 0 into row 1 and row 2 into row 3 (row_bcast:15 on rows 1 and 3), rows 0-1
+// into rows 2-3 (row_bcast:31 on rows 2 and 3); lane 63 holds the
+// wavefront's result.  All lanes must be active.  The values reduced are
+// non-negative floats (alpha, +inf in the minimum and +0 in the maximum for
+// a lane without sites), whose bit patterns order as unsigned integers: the
+// steps are integer min / max, exact and free of the NaN quieting that
+// float min / max apply to their operands.
+// The moved value of a lane outside the row mask is the operation's
+// identity ID, so that the move folds into the min / max instruction.
+template <int CTRL, int ROW_MASK, uint32_t ID>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)ID, (int)v, CTRL, ROW_MASK, 0xf, false);
 }
-template <class OP>
-__device__ __forceinline__ float wreduce_dpp(float v, OP op) {
-  v = op(v, dpp_f32<0xB1>(v));        // quad_perm [1,0,3,2]
-  v = op(v, dpp_f32<0x4E>(v));        // quad_perm [2,3,0,1]
-  v = op(v, dpp_f32<0x141>(v));       // row_half_mirror
-  v = op(v, dpp_f32<0x140>(v));       // row_mirror
-  v = op(v, dpp_f32<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
-  v = op(v, dpp_f32<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+template <uint32_t ID, class OP>
+__device__ __forceinline__ uint32_t wreduce_dpp(uint32_t v, OP op) {
+  v = op(v, dpp_u32<0xB1, 0xf, ID>(v));   // quad_perm [1,0,3,2]
+  v = op(v, dpp_u32<0x4E, 0xf, ID>(v));   // quad_perm [2,3,0,1]
+  v = op(v, dpp_u32<0x141, 0xf, ID>(v));  // row_half_mirror
+  v = op(v, dpp_u32<0x140, 0xf, ID>(v));  // row_mirror
+  v = op(v, dpp_u32<0x142, 0xA, ID>(v));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_u32<0x143, 0xC, ID>(v));  // row_bcast:31 into rows 2, 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
-__device__ __forceinline__ float wminf(float v) {
-  return wreduce_dpp(v, [](float a, float b) { return fminf(a, b); });
+__device__ __forceinline__ float wmin_nonneg(float v) {
+  return __builtin_bit_cast(float, wreduce_dpp<0xffffffffu>(
+                                        __builtin_bit_cast(uint32_t, v),
+                                        [](uint32_t a, uint32_t b) { return a < b ? a : b; }));
 }
-__device__ __forceinline__ float wmaxf(float v) {
-  return wreduce_dpp(v, [](float a, float b) { return fmaxf(a, b); });
+__device__ __forceinline__ float wmax_nonneg(float v) {
+  return __builtin_bit_cast(float, wreduce_dpp<0u>(
+                                        __builtin_bit_cast(uint32_t, v),
+                                        [](uint32_t a, uint32_t b) { return a > b ? a : b; }));
 }
 
 // Wavefront reductions, then a fixed-order combination over the block's
@@ -1147,7 +1155,7 @@ __device__ void store_records(const Acc& a, const SimDesc& d, int slot) {
   const bool sums = (d.diag & kDiagSums) != 0;
   uint32_t it = 0;
   if constexpr (ITERS) it = (uint32_t)wsumi(a.iters);
-  const float mn = wminf(a.amin), mx = wmaxf(a.amax);
+  const float mn = wmin_nonneg(a.amin), mx = wmax_nonneg(a.amax);
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (sums) {
     v[0] = wsum(a.rho);
