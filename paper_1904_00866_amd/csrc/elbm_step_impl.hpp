@@ -1382,6 +1382,60 @@ __device__ __forceinline__ void moments_of(const G& g, R& rho, R (&j)[3]) {
   }
   if constexpr (D > 2) j[2] = cz[1] - cz[2];
 }
+// rho - rho_ref and rho u from the deviations s_i, in FP32.  With
+// W_i = 4^z(i) / 6^D (z: the number of zero components of c_i), the sums
+// sum_i W_i s_i and sum_i W_i c_i s_i are 6^-D times sums of 4^z(i) s_i,
+// whose factors 4 are exact.  They are formed axis by axis: per source row
+// (c_y, c_z), a = 4 s_0 + (s_+ + s_-) and b = s_+ - s_-; over c_y the same
+// on the rows' a and b, with a_+ - a_- for the y momentum; then over c_z.
+// 6^-D is applied once, in two FP32 parts: its FP32 rounding alone would
+// scale every moment by the same wrong factor at every step, a bias that
+// the collision hands on to the state.
+template <int D, class G>
+__device__ __forceinline__ void moments_w4(const G& s, float& dr, float (&j)[3]) {
+  constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
+  float ax[3][3], bx[3][3];  // [c_y][c_z]
+#pragma unroll
+  for (int dz = 0; dz < NZ; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < NY; ++dy) {
+      const int i0 = 9 * dz + 3 * dy;
+      const float s0 = s(i0), sp = s(i0 + 1), sm = s(i0 + 2);
+      ax[dy][dz] = fmaf(4.0f, s0, sp + sm);
+      bx[dy][dz] = sp - sm;
+    }
+  float ay[3], by[3], cy[3];  // [c_z]
+#pragma unroll
+  for (int dz = 0; dz < NZ; ++dz) {
+    if constexpr (D > 1) {
+      ay[dz] = fmaf(4.0f, ax[0][dz], ax[1][dz] + ax[2][dz]);
+      by[dz] = fmaf(4.0f, bx[0][dz], bx[1][dz] + bx[2][dz]);
+      cy[dz] = ax[1][dz] - ax[2][dz];
+    } else {
+      ay[dz] = ax[0][dz];
+      by[dz] = bx[0][dz];
+      cy[dz] = 0.0f;
+    }
+  }
+  float S, J[3];
+  if constexpr (D > 2) {
+    S = fmaf(4.0f, ay[0], ay[1] + ay[2]);
+    J[0] = fmaf(4.0f, by[0], by[1] + by[2]);
+    J[1] = fmaf(4.0f, cy[0], cy[1] + cy[2]);
+    J[2] = ay[1] - ay[2];
+  } else {
+    S = ay[0];
+    J[0] = by[0];
+    J[1] = cy[0];
+    J[2] = 0.0f;
+  }
+  constexpr double c = 1.0 / Lattice<D>::den();
+  constexpr float ch = float(c), cl = float(c - double(float(c)));
+  dr = fmaf(ch, S, cl * S);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) j[a] = a < D ? fmaf(ch, J[a], cl * J[a]) : 0.0f;
+}
+
 template <int D, class S, class R>
 __device__ __forceinline__ void site_moments(const Site<D, S, R>& v, R& rho, R (&j)[3]) {
   moments_of<D>([&](int i) { return v.g(i); }, rho, j);
@@ -1428,17 +1482,8 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
   v.site = sl;
   v.desc = &d;
   v.r = float(d.rho_ref);
-  // W_i s_i with W_i = wh + wl, rounded once: with the FP32 weight alone the
-  // moments are biased by float(W_i) / W_i, and the collision hands the bias
-  // on to the state at every step (rho u grows by about alpha beta 2e-8 per
-  // step)
   float dr, j32[3];
-  moments_of<D>(
-      [&](int i) {
-        const float si = v.s(i);
-        return fmaf(float(L::W(i)), si, SiteDev<D, S>::w_lo(L::W(i)) * si);
-      },
-      dr, j32);
+  moments_w4<D>([&](int i) { return v.s(i); }, dr, j32);
   const float rho32 = v.r + dr;
   // FP32 arithmetic: the hardware reciprocal refined by one Newton step
   // (e = 1 - rho r, r <- r + r e) and the hardware square root (1 ulp)
