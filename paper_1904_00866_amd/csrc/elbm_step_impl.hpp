@@ -814,14 +814,14 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
     }
     const float Dv = E - O;
     o.D = R(Dv);
-    o.guard = !(R(Dv) > Prec<R>::guard * v.rho);
+    o.guard = !(Dv > float(Prec<R>::guard) * v.rho32);
     o.accepted2 = o.guard || !(O > 0.0f);
     o.alpha = R(2);
     if (!o.accepted2) {
       const float Ds = E + O;
       const float r0 = __builtin_amdgcn_rcpf(Ds);
       const float r = fmaf(r0, fmaf(-Ds, r0, 1.0f), r0);
-      o.alpha = fmax(R(2) - R(2.0f * O * r), R(1));
+      o.alpha = R(2) - R(fminf(2.0f * O * r, 1.0f));  // clamped to [1, 2]
       o.iters = 1;
     }
     return o;
@@ -1511,28 +1511,35 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
   // one reciprocal, 1 / (rho P_x P_y), times 1/rho's; z has its own.  Each
   // quotient carries a few FP32 roundings (the hardware reciprocal is good to
   // 1 ulp).
-  float C[3][3], P[3];
+  float F[3][3], C[3][3], P[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
-      const float F0 = 1.0f + dl[a][0], Fp = 1.0f + dl[a][1], Fm = 1.0f + dl[a][2];
-      C[a][0] = Fp * Fm;
-      C[a][1] = F0 * Fm;
-      C[a][2] = F0 * Fp;
-      P[a] = F0 * C[a][0];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[a][c] = 1.0f + dl[a][c];
+      C[a][0] = F[a][1] * F[a][2];
+      C[a][1] = F[a][0] * F[a][2];
+      C[a][2] = F[a][0] * F[a][1];
+      P[a] = F[a][0] * C[a][0];
     } else {
-      C[a][0] = C[a][1] = C[a][2] = P[a] = 1.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) F[a][c] = C[a][c] = 1.0f;
+      P[a] = 1.0f;
     }
   }
   const float Rxy = irho * __builtin_amdgcn_rcpf(D > 1 ? P[0] * P[1] : P[0]);
+  // s^eq_i = dr + rho (F_x F_y F_z - 1), expanded so that no term cancels:
+  // seqA = dr + rho (F_x F_y - 1) = (dr + rho dl_x) + (rho dl_y) F_x and
+  // seqB = rho F_x F_y, then s^eq_i = seqA + seqB dl_z
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float Rx = Rxy * C[0][a];
+    const float Ax = fmaf(rho32, dl[0][a], dr);
+    const float RFx = rho32 * F[0][a];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const float dxy = D > 1 ? fmaf(dl[0][a], dl[1][b], dl[0][a] + dl[1][b]) : dl[0][a];
-      v.seqA[a][b] = fmaf(rho32, dxy, dr);
-      v.seqB[a][b] = fmaf(rho32, dxy, rho32);
+      v.seqA[a][b] = D > 1 ? fmaf(rho32 * dl[1][b], F[0][a], Ax) : Ax;
+      v.seqB[a][b] = D > 1 ? RFx * F[1][b] : RFx;
       v.rxy[a][b] = D > 1 ? Rx * C[1][b] : Rx;
     }
   }
@@ -1560,6 +1567,19 @@ struct SiteOut {
 
 // Diagnostics of one updated site of an entropic mode: per-lane values
 // here, count predicates returned.
+// Whether rho, u and alpha of a site are all finite (one product carries a
+// NaN or infinity of any factor; the trailing + rho catches a zero product).
+// The mixed site's values are FP32 numbers and are tested in FP32.
+template <class V, class R>
+__device__ __forceinline__ bool site_finite(const V& v, R alpha) {
+  return isfinite(v.rho * alpha * v.u[0] * v.u[1] * v.u[2] + v.rho);
+}
+template <int D, class S>
+__device__ __forceinline__ bool site_finite(const SiteDev<D, S>& v, double alpha) {
+  return isfinite(v.rho32 * float(alpha) * float(v.u[0]) * float(v.u[1]) * float(v.u[2]) +
+                  v.rho32);
+}
+
 template <bool SUMS, class V, class R>
 __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bool live,
                                             const V& v, const AlphaOut<R>& ao,
@@ -1572,7 +1592,7 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
       flags = flag(kCntAccept2, ao.accepted2) | flag(kCntAstarLt2, ao.astar_lt2) |
               flag(kCntAlphaLt2, alpha < R(2)) | flag(kCntGuard, ao.guard) |
               flag(kCntFallback, ao.fallback) | flag(kCntNeg, ftmin < R(0)) |
-              flag(kCntNonfinite, !isfinite(rho * alpha * v.u[0] * v.u[1] * v.u[2] + rho));
+              flag(kCntNonfinite, !site_finite(v, alpha));
     if (live) acc.iters += ao.iters;
     if (SUMS && live && (diag & kDiagSums)) {
       // H(f) = H(f^eq) + D
