@@ -793,8 +793,13 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // The root solvers need alpha_max on every lane; the closed form and the
   // secant need it only where alpha_* < 2, which the tiers below detect.
   constexpr bool kXmax = (MODE == kNewton || MODE == kBisect);
-  // 2-byte storage: the first-term sums in FP32 (sums_k1)
-  constexpr bool kS16 = sizeof(typename V::T) == 2 && std::is_same<R, double>::value;
+  // The closed form on 2-byte storage takes the first-term sums (and, on the
+  // mixed site, forms them in FP32: sums_k1).  The root solvers keep the full
+  // tiers: their root moves with D itself, by about x^2 / 12 under the
+  // one-term truncation, while Eq. (9) depends on the ratio O / (E + O),
+  // in which the truncations of E and O largely cancel.
+  constexpr bool kS16 =
+      sizeof(typename V::T) == 2 && std::is_same<R, double>::value && MODE == kClosed;
   constexpr bool kK1 = kS16 && V::kSumsK1 && !kXmax;
   if constexpr (kK1 && MODE == kClosed && PHASE == kPhaseCommon) {
     // The common phase of the closed form on them, in FP32: alpha_* = 2
@@ -830,13 +835,13 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   // from the source buffer; their source offsets (v.w) are formed just
   // before each such pass rather than kept live through the whole update.
   // Common tier: x_i, max|x_i| and the KC-term series sums in one pass.
-  // With 2-byte storage the stored result carries 11 bits: one term
-  // (E = sum f^eq x^2 / 2, O = sum f^eq x^3 / 6) up to max|x_i| <= thrM =
-  // 0.025 leaves out x^4/12 of E and x^5/20 of O, which moves 2 - alpha
-  // (<= 2|x|/3) by at most 0.47 x^2 of itself, alpha by at most 5e-6 and
-  // f~_i = f^eq_i (1 + (1 - alpha beta) x_i) by at most 1.3e-7 f^eq_i: about
-  // 2 % of half a unit of an FP16 deviation s_i of the size of x_i.  With 4-
-  // and 8-byte storage the tiers keep alpha to 2^-53.
+  // With 2-byte storage the stored result carries 11 bits: for the closed
+  // form one term (E = sum f^eq x^2 / 2, O = sum f^eq x^3 / 6) up to
+  // max|x_i| <= thrM = 0.025 leaves out x^4/12 of E and x^5/20 of O, which
+  // moves 2 - alpha (<= 2|x|/3) by at most 0.47 x^2 of itself, alpha by at
+  // most 5e-6 and f~_i = f^eq_i (1 + (1 - alpha beta) x_i) by at most
+  // 1.3e-7 f^eq_i: about 2 % of half a unit of an FP16 deviation s_i of the
+  // size of x_i.  Otherwise the tiers keep alpha to 2^-53.
   constexpr int KC = kS16 ? 1 : Base<R>::K;
   const R thrC = kS16 ? Base<R>::thrM : Base<R>::thr;
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);

@@ -300,34 +300,75 @@ def test_one_step_row_aligned_boxes(gpu, orc, D, storage, mode):
 GROUP_SHAPES = [(2048, 1, 1), (1024, 3, 1), (2048, 2, 1)]
 
 
+def _storage_rounding(storage, fo, W):
+    """Half a unit in the last place of each output in its storage format
+    (with 1 % slack), the bound of one rounding of an exact result."""
+    if storage == "f32":
+        return 2.0 ** -24 * np.abs(fo) * 1.01 + 1e-300
+    if storage == "f32dev":
+        return W * (2.0 ** -24 * np.abs(fo / W - 1.0) * 1.01 + 1e-12)
+    return W * (2.0 ** -11 * np.abs(fo / W - 1.0) * 1.01 + 2.0 ** -24)
+
+
 @pytest.mark.parametrize("shape", GROUP_SHAPES)
 @pytest.mark.parametrize("storage", ["f32", "f32dev", "f16dev"])
-@pytest.mark.parametrize("mode", ["closed", "bgk"])
+@pytest.mark.parametrize("mode", ["closed", "bgk", "mixed"])
 def test_one_step_row_group_boxes(gpu, orc, shape, storage, mode):
     """With 4- and 2-byte storage the D1Q3 and D2Q9 kernels update four
     tiles per workgroup; when the x-rows hold whole groups of them, the loads
     of every tile take the first tile's offsets shifted by a scalar, and only
     the first tile's x - 1 and the last tile's x + 1 wrap around the row.
-    One step against the oracle from the decoded stored state, to one output
-    rounding, on every site (both wraps included)."""
+    One step against the oracle from the decoded stored state, on every site
+    (both wraps included): to one output rounding with FP64 site arithmetic
+    (closed form, LBGK); with mixed arithmetic (closed form) to 2e-6
+    relative plus one output rounding, as the other mixed one-step tests."""
     D = 1 if shape[1] == 1 else 2
     N = int(np.prod(shape))
     f0 = _random_state(D, N, seed=760 + 10 * D + len(storage) + len(mode) + shape[1],
                        eps=0.02, tilt=0.05)
-    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.97, mode=mode)
+    arith = "mixed" if mode == "mixed" else True
+    amode = "closed" if mode == "mixed" else mode
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.97, mode=amode, fp64=arith)
     fq = sim.populations().cpu().numpy()
     sim.step(1)
     fg = sim.populations().cpu().numpy()
-    fo, _, _ = orc.step(_ocfg(orc, D, shape, beta=0.97, mode=mode), fq)
+    fo, _, _ = orc.step(_ocfg(orc, D, shape, beta=0.97, mode=amode), fq)
     W = H.textbook_weights(D)[:, None]
-    if storage == "f32":
-        tol = 2.0 ** -24 * np.abs(fo) * 1.01 + 1e-300
-    elif storage == "f32dev":
-        tol = W * (2.0 ** -24 * np.abs(fo / W - 1.0) * 1.01 + 1e-12)
-    else:
-        tol = W * (2.0 ** -11 * np.abs(fo / W - 1.0) * 1.01 + 2.0 ** -24)
+    tol = _storage_rounding(storage, fo, W)
+    if mode == "mixed":
+        tol = tol + 2e-6 * np.abs(fo)
     assert np.all(np.abs(fg - fo) <= tol)
     sim.close()
+
+
+@pytest.mark.parametrize("shape", [SHAPES[2], (1024, 3, 1)])
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("mode", ["secant", "newton"])
+def test_one_step_root_modes_reduced_storage(gpu, orc, shape, storage, mode):
+    """The root-solver modes with 4- and 2-byte storage on D2Q9, whose
+    kernels update four tiles per workgroup (general and grouped-row loads),
+    near and far from equilibrium in one state: one step against the oracle
+    from the decoded stored state to one output rounding (the two alphas
+    differ by the solvers' stopping rounding, far below it)."""
+    N = int(np.prod(shape))
+    W1 = H.textbook_weights(2)
+    near = _random_state(2, N, seed=780 + len(storage) + len(mode), eps=0.02, tilt=0.05)
+    far = Wk.random_populations(W1, N, 0.7, 790 + len(mode), tilt=0.2, log_uniform_eps=False)
+    pick = np.random.default_rng(791).random(N) < 0.2
+    f0 = np.ascontiguousarray(np.where(pick[None, :], far, near))
+    sim = _sim(gpu, 2, shape, f0, storage=storage, beta=0.9, mode=mode, root_max_iter=200,
+               diag=gpu.DIAG_COUNTS)
+    fq = sim.populations().cpu().numpy()
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    st = sim.stats()
+    sim.close()
+    fo, _, d = orc.step(_ocfg(orc, 2, shape, beta=0.9, mode=mode, root_max_iter=200), fq,
+                        want_diag=True)
+    assert d["n_alphastar_lt2"] > 0 and st["n_alphastar_lt2"] == d["n_alphastar_lt2"]
+    W = W1[:, None]
+    tol = _storage_rounding(storage, fo, W) + 1e-12 * np.abs(fo)
+    assert np.all(np.abs(fg - fo) <= tol), np.max(np.abs(fg - fo) / tol)
 
 
 def test_fp32_arithmetic_ablation(gpu, orc):
