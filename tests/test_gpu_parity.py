@@ -343,13 +343,19 @@ def test_one_step_row_group_boxes(gpu, orc, shape, storage, mode):
 
 @pytest.mark.parametrize("shape", [SHAPES[2], (1024, 3, 1)])
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
-@pytest.mark.parametrize("mode", ["secant", "newton"])
-def test_one_step_root_modes_reduced_storage(gpu, orc, shape, storage, mode):
-    """The root-solver modes with 4- and 2-byte storage on D2Q9, whose
-    kernels update four tiles per workgroup (general and grouped-row loads),
-    near and far from equilibrium in one state: one step against the oracle
-    from the decoded stored state to one output rounding (the two alphas
-    differ by the solvers' stopping rounding, far below it)."""
+@pytest.mark.parametrize("mode", ["closed", "secant", "newton", "bisect"])
+def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
+    """Every alpha mode with 4- and 2-byte storage on D2Q9, whose kernels
+    update four tiles per workgroup (general and grouped-row loads), on a
+    state with near- and far-from-equilibrium sites (alpha_* < 2 and the
+    rare tier on some): one step against the oracle from the decoded stored
+    state to one output rounding (the two alphas differ by the solvers'
+    stopping rounding, far below it).  Bisection stops anywhere in its
+    window -tol <= G <= 0, which near equilibrium (G' ~ 1e-8) spans alphas
+    1e-5 apart, so the two sides often stop at different midpoints: where
+    the two alphas differ, the GPU's is checked against the window with the
+    oracle's G, and the populations of the other sites (at least half) are
+    compared."""
     N = int(np.prod(shape))
     W1 = H.textbook_weights(2)
     near = _random_state(2, N, seed=780 + len(storage) + len(mode), eps=0.02, tilt=0.05)
@@ -357,18 +363,27 @@ def test_one_step_root_modes_reduced_storage(gpu, orc, shape, storage, mode):
     pick = np.random.default_rng(791).random(N) < 0.2
     f0 = np.ascontiguousarray(np.where(pick[None, :], far, near))
     sim = _sim(gpu, 2, shape, f0, storage=storage, beta=0.9, mode=mode, root_max_iter=200,
-               diag=gpu.DIAG_COUNTS)
+               diag=gpu.DIAG_COUNTS | gpu.DIAG_ALPHA)
     fq = sim.populations().cpu().numpy()
     sim.step(1)
     fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
     st = sim.stats()
     sim.close()
-    fo, _, d = orc.step(_ocfg(orc, 2, shape, beta=0.9, mode=mode, root_max_iter=200), fq,
-                        want_diag=True)
+    fo, ao, d = orc.step(_ocfg(orc, 2, shape, beta=0.9, mode=mode, root_max_iter=200), fq,
+                         want_alpha=True, want_diag=True)
     assert d["n_alphastar_lt2"] > 0 and st["n_alphastar_lt2"] == d["n_alphastar_lt2"]
     W = W1[:, None]
     tol = _storage_rounding(storage, fo, W) + 1e-12 * np.abs(fo)
-    assert np.all(np.abs(fg - fo) <= tol), np.max(np.abs(fg - fo) / tol)
+    ok = np.abs(fg - fo) <= tol
+    if mode == "bisect":
+        same = np.abs(ag - ao) <= 1e-14
+        assert same.mean() > 0.5
+        ok = ok | ~same[_source_sites(2, shape)]
+        for s in np.nonzero(~same)[0]:
+            g = orc.G(2, fq[:, s], ag[s])
+            assert -1e-13 - 1e-16 <= g <= 1e-16, (s, g)
+    assert np.all(ok), np.max(np.abs(fg - fo) / tol)
 
 
 def test_fp32_arithmetic_ablation(gpu, orc):
@@ -416,17 +431,19 @@ def test_mixed_arithmetic_one_step(gpu, orc, D, rows, storage):
 
 
 @pytest.mark.parametrize("D", [2, 3])
-def test_mixed_arithmetic_far_from_equilibrium(gpu, orc, D):
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_mixed_arithmetic_far_from_equilibrium(gpu, orc, D, storage):
     """The rare tier under mixed arithmetic (alpha_* < 2 on many sites, the
-    log1p forms, the rolled FP32 collision): one step, FP32 storage, error
-    4e-6 of the larger of the old and new population (far from equilibrium
-    the FP32 term alpha beta (f^eq_i - f_i) can exceed both populations, and
-    f^eq_i carries the FP32 equilibrium's rounding)."""
+    log1p forms, the rolled FP32 collision): one step, FP32 and FP16
+    deviation storage, error 4e-6 of the larger of the old and new
+    population (far from equilibrium the FP32 term alpha beta (f^eq_i - f_i)
+    can exceed both populations, and f^eq_i carries the FP32 equilibrium's
+    rounding), plus one output rounding with FP16 storage."""
     shape = SHAPES[D]
     N = int(np.prod(shape))
     f0 = Wk.random_populations(H.textbook_weights(D), N, 0.7, 940 + D, tilt=0.2,
                                log_uniform_eps=False)
-    sim = _sim(gpu, D, shape, f0, storage="f32", beta=0.9, fp64="mixed",
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.9, fp64="mixed",
                diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS)
     fq = sim.populations().cpu().numpy()
     sim.step(1)
@@ -434,10 +451,13 @@ def test_mixed_arithmetic_far_from_equilibrium(gpu, orc, D):
     ag = sim.alpha_field().cpu().numpy()
     fo, ao, d = orc.step(_ocfg(orc, D, shape, beta=0.9), fq, want_alpha=True, want_diag=True)
     assert d["n_alphastar_lt2"] > N // 20
-    r = np.abs(fg - fo) / np.maximum(np.abs(fo), np.abs(fq))
+    tol = 4e-6 * np.maximum(np.abs(fo), np.abs(fq))
+    if storage == "f16dev":
+        tol = tol + _storage_rounding(storage, fo, H.textbook_weights(D)[:, None])
+    r = np.abs(fg - fo) / tol
     k = np.unravel_index(np.argmax(r), r.shape)
     s = k[1]
-    assert r[k] <= 4e-6, (r[k], k, ag[s], ao[s], fq[:, s], fo[:, s], fg[:, s])
+    assert r[k] <= 1.0, (r[k], k, ag[s], ao[s], fq[:, s], fo[:, s], fg[:, s])
     assert np.max(np.abs(ag - ao)) <= 1e-5
     assert sim.stats()["n_alphastar_lt2"] == d["n_alphastar_lt2"]
     sim.close()
