@@ -341,28 +341,29 @@ def test_one_step_row_group_boxes(gpu, orc, shape, storage, mode):
     sim.close()
 
 
-@pytest.mark.parametrize("shape", [SHAPES[2], (1024, 3, 1)])
+@pytest.mark.parametrize("shape", [SHAPES[2], (1024, 3, 1), SHAPES[3]])
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 @pytest.mark.parametrize("mode", ["closed", "secant", "newton", "bisect"])
 def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
-    """Every alpha mode with 4- and 2-byte storage on D2Q9, whose kernels
-    update four tiles per workgroup (general and grouped-row loads), on a
-    state with near- and far-from-equilibrium sites (alpha_* < 2 and the
-    rare tier on some): one step against the oracle from the decoded stored
-    state to one output rounding (the two alphas differ by the solvers'
-    stopping rounding, far below it).  Bisection stops anywhere in its
+    """Every alpha mode with 4- and 2-byte storage on D2Q9 (whose kernels
+    update four tiles per workgroup; general and grouped-row loads) and
+    D3Q27, on a state with near- and far-from-equilibrium sites (alpha_* < 2
+    and the rare tier on some): one step against the oracle from the decoded
+    stored state to one output rounding (the two alphas differ by the
+    solvers' stopping rounding, far below it).  Bisection stops anywhere in its
     window -tol <= G <= 0, which near equilibrium (G' ~ 1e-8) spans alphas
     1e-5 apart, so the two sides often stop at different midpoints: where
     the two alphas differ, the GPU's is checked against the window with the
     oracle's G, and the populations of the other sites (at least half) are
     compared."""
+    D = 3 if shape[2] > 1 else 2
     N = int(np.prod(shape))
-    W1 = H.textbook_weights(2)
-    near = _random_state(2, N, seed=780 + len(storage) + len(mode), eps=0.02, tilt=0.05)
+    W1 = H.textbook_weights(D)
+    near = _random_state(D, N, seed=780 + len(storage) + len(mode), eps=0.02, tilt=0.05)
     far = Wk.random_populations(W1, N, 0.7, 790 + len(mode), tilt=0.2, log_uniform_eps=False)
     pick = np.random.default_rng(791).random(N) < 0.2
     f0 = np.ascontiguousarray(np.where(pick[None, :], far, near))
-    sim = _sim(gpu, 2, shape, f0, storage=storage, beta=0.9, mode=mode, root_max_iter=200,
+    sim = _sim(gpu, D, shape, f0, storage=storage, beta=0.9, mode=mode, root_max_iter=200,
                diag=gpu.DIAG_COUNTS | gpu.DIAG_ALPHA)
     fq = sim.populations().cpu().numpy()
     sim.step(1)
@@ -370,7 +371,7 @@ def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
     ag = sim.alpha_field().cpu().numpy()
     st = sim.stats()
     sim.close()
-    fo, ao, d = orc.step(_ocfg(orc, 2, shape, beta=0.9, mode=mode, root_max_iter=200), fq,
+    fo, ao, d = orc.step(_ocfg(orc, D, shape, beta=0.9, mode=mode, root_max_iter=200), fq,
                          want_alpha=True, want_diag=True)
     assert d["n_alphastar_lt2"] > 0 and st["n_alphastar_lt2"] == d["n_alphastar_lt2"]
     W = W1[:, None]
@@ -379,9 +380,9 @@ def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
     if mode == "bisect":
         same = np.abs(ag - ao) <= 1e-14
         assert same.mean() > 0.5
-        ok = ok | ~same[_source_sites(2, shape)]
+        ok = ok | ~same[_source_sites(D, shape)]
         for s in np.nonzero(~same)[0]:
-            g = orc.G(2, fq[:, s], ag[s])
+            g = orc.G(D, fq[:, s], ag[s])
             assert -1e-13 - 1e-16 <= g <= 1e-16, (s, g)
     assert np.all(ok), np.max(np.abs(fg - fo) / tol)
 
