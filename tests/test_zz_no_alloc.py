@@ -23,12 +23,12 @@ def _state(D, N, seed):
     return np.ascontiguousarray(np.where(pick[None, :], far, near))
 
 
-def _compare(gpu, D, shape, nsteps, seed, mode, dev_stats):
+def _compare(gpu, D, shape, nsteps, seed, mode, dev_stats, storage="f64", arith=True):
     nx, ny, nz = shape
     N = nx * ny * nz
     f0 = _state(D, N, seed)
     rho, u = np.ones(N), np.zeros((D, N))
-    kw = dict(storage="f64", beta=0.97, mode=mode)
+    kw = dict(storage=storage, beta=0.97, mode=mode, fp64=arith)
     a = gpu.Simulation(D, nx, ny, nz, rho0=rho, u0=u,
                        diag=gpu.DIAG_ALPHA | gpu.DIAG_COUNTS | gpu.DIAG_SUMS, **kw)
     b = gpu.Simulation(D, nx, ny, nz, rho0=rho, u0=u, diag=gpu.DIAG_ALPHA, **kw)
@@ -59,6 +59,17 @@ def test_step_noalloc_matches_step_and_stats(gpu):
     _compare(gpu, 3, (40, 36, 30), 3, 9100, "closed", dev_stats)
     _compare(gpu, 2, (37, 23, 1), 2, 9200, "closed", dev_stats)
     _compare(gpu, 2, (64, 12, 1), 2, 9300, "newton", dev_stats)
+
+
+def test_step_noalloc_four_tile_kernels(gpu):
+    """The kernels that update four tiles per workgroup (D2Q9 with 4- and
+    2-byte storage: one record per four tiles), on general and grouped-row
+    boxes, FP64 and mixed site arithmetic, each against elbm_step bit for
+    bit, in a row on one scratch."""
+    dev_stats = torch.zeros(gpu.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    _compare(gpu, 2, (1024, 6, 1), 2, 9400, "closed", dev_stats, storage="f16dev", arith="mixed")
+    _compare(gpu, 2, (37, 23, 1), 2, 9500, "closed", dev_stats, storage="f32")
+    _compare(gpu, 2, (1024, 2, 1), 3, 9600, "secant", dev_stats, storage="f16dev")
 
 
 def test_step_noalloc_rejects_boxes_beyond_the_scratch(gpu):
