@@ -208,25 +208,36 @@ elbm_status elbm_set_populations(elbm_sim *sim, const double *f);
 /* Advance nsteps >= 0 time steps (Eq. (1) then Eq. (5b) per step). */
 elbm_status elbm_step(elbm_sim *sim, int64_t nsteps);
 
-/* rho[N] and u[D*N] of the current f(x,t) (float64). */
+/* The moments of the current f(x,t) that the equilibrium is constrained to
+ * (the conditions of the minimisation of Eq. (3)): rho = sum_i f_i into
+ * rho[N] and u = sum_i c_i f_i / rho into u[D*N], component-major (u[a*N +
+ * s]); device pointers, float64, written on the simulation's stream. */
 elbm_status elbm_moments(elbm_sim *sim, double *rho, double *u);
 
-/* Current pre-collision populations f(x,t) as float64 f[Q*N]. */
+/* Current pre-collision populations f_i(x,t) (the streamed values of
+ * Eq. (5b)) decoded from their storage format into f[Q*N] (device,
+ * float64, direction-major: f[i*N + s]). */
 elbm_status elbm_populations(elbm_sim *sim, double *f);
 
 /* Gather at n sites (site indices sites[n], int64, device):
- *   which = 0: the pre-collision f(x,t) of those sites;
- *   which = 1: the post-collision f~(x,t-1) the last step wrote there.
- * out[i*n + k] (float64). */
+ *   which = 0: the pre-collision f(x,t) of those sites (Eq. (5b));
+ *   which = 1: the post-collision f~(x,t-1) of Eq. (1) that the last step
+ *              wrote there.
+ * out[i*n + k] (device, float64). */
 elbm_status elbm_gather(elbm_sim *sim, const int64_t *sites, int64_t n,
                         int32_t which, double *out);
 
-/* alpha(x) used by the most recent step (requires ELBM_DIAG_ALPHA and at
- * least one step), copied into alpha[N] (float64). */
+/* alpha(x) of the collision Eq. (1) in the most recent step: Eq. (8)-(9)
+ * for the closed form, the root of Eq. (4) for Newton and bisection, the
+ * modified secant's last iterate, 2 for LBGK (requires ELBM_DIAG_ALPHA and
+ * at least one step), copied into alpha[N] (device, float64). */
 elbm_status elbm_alpha_field(elbm_sim *sim, double *alpha);
 
 /* Diagnostics of the most recent step (requires ELBM_DIAG_COUNTS and at
- * least one step).  stats is a HOST pointer; synchronises the stream. */
+ * least one step): the counts of elbm_stats_t (sites accepting alpha = 2,
+ * the quantity of the Fig. 5 discussion; alpha_* < 2 by Eq. (8); ...) and,
+ * with ELBM_DIAG_SUMS, sum_x H of Eq. (6).  stats is a HOST pointer;
+ * synchronises the stream. */
 elbm_status elbm_stats(elbm_sim *sim, elbm_stats_t *stats);
 
 /* Time t of the current state (host value, no synchronisation). */
