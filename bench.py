@@ -205,7 +205,7 @@ def _serving_summary(res, rate):
 def serving_block(args) -> dict:
     """Two seeded Poisson streams of D2Q9 shear-layer requests through the
     continuous-batching server: the overloaded stream (arrivals faster than
-    the GPU can serve) and one below capacity; four sampled requests rerun
+    the GPU can serve) and one below capacity; eight sampled requests rerun
     alone and compared with their in-mix results."""
     import numpy as np
     import torch
@@ -217,7 +217,7 @@ def serving_block(args) -> dict:
     reqs = Wk.serving_stream(args.serving_requests, rate=args.serving_rate)
     rng = np.random.default_rng(1)
     cand = [r["k"] for r in reqs if r["n"] <= 1024]
-    sample = sorted(int(k) for k in rng.choice(cand, size=min(4, len(cand)), replace=False))
+    sample = sorted(int(k) for k in rng.choice(cand, size=min(8, len(cand)), replace=False))
     log(f"serving: {len(reqs)} requests at {args.serving_rate}/s")
     res = serving.run_stream(reqs, max_active=max_active, round_steps=round_steps,
                              keep=sample, log=log)
