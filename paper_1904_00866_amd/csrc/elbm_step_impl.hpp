@@ -420,6 +420,7 @@ struct SiteDev {
   // per-axis factors (and 1/rho) give it with one product per direction
   float rxy[3][3];     // 1 / (rho (1 + dl_x(dx)) (1 + dl_y(dy)))
   float rlz[3];        // 1 / (1 + dl_z(dz))
+  float dd[Q];         // s_i - s^eq_i as sums_k1 formed them, for the collision
   const T* src;
   uint32_t site;
   const SimDesc* desc;
@@ -477,13 +478,14 @@ struct SiteDev {
   // f^eq_i x_i = W_i d_i, so E and O are W-weighted sums of d_i x_i and
   // d_i x_i^2, summed per weight class (W_i = 4^z / 6^D, z the number of
   // zero components of c_i) and weighted once at the end.
-  __device__ __forceinline__ void sums_k1(const Pass& p, float& sE, float& sO, float& xabs) const {
+  __device__ __forceinline__ void sums_k1(const Pass& p, float& sE, float& sO, float& xabs) {
     float e[D + 1], o[D + 1], xm = 0.0f;
 #pragma unroll
     for (int z = 0; z <= D; ++z) e[z] = o[z] = 0.0f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const float di = s(i) - seq(i, p);
+      dd[i] = di;
       const float xi = di * rfac(i, p);
       const float t = di * xi;
       const int z = L::nzero(i);
@@ -1646,7 +1648,12 @@ __device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float si = v.s(i);
-    const float sn = fmaf(ab, v.seq(i, P) - si, si);
+    // the common phase of the closed form on 2-byte storage reuses the
+    // deviations s_i - s^eq_i of its sums (sums_k1): keeping those 27 values
+    // live costs fewer registers than keeping the factors s^eq_i is
+    // recomputed from
+    constexpr bool kDD = sizeof(T) == 2 && MODE == kClosed && PHASE == kPhaseCommon;
+    const float sn = kDD ? fmaf(-ab, v.dd[i], si) : fmaf(ab, v.seq(i, P) - si, si);
     if constexpr (PHASE != kPhaseCommon) tmin = fminf(tmin, v.r + sn);
     st_nt<T>(blk + i * kLane * es, kLane * es, lo, v.enc(i, sn));
     sched_group(i);
