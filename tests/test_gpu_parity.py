@@ -341,22 +341,22 @@ def test_one_step_row_group_boxes(gpu, orc, shape, storage, mode):
     sim.close()
 
 
-@pytest.mark.parametrize("shape", [SHAPES[2], (1024, 3, 1), SHAPES[3]])
+@pytest.mark.parametrize("shape", [SHAPES[1], (2048, 1, 1), SHAPES[2], (1024, 3, 1), SHAPES[3]])
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 @pytest.mark.parametrize("mode", ["closed", "secant", "newton", "bisect"])
 def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
-    """Every alpha mode with 4- and 2-byte storage on D2Q9 (whose kernels
-    update four tiles per workgroup; general and grouped-row loads) and
-    D3Q27, on a state with near- and far-from-equilibrium sites (alpha_* < 2
-    and the rare tier on some): one step against the oracle from the decoded
-    stored state to one output rounding (the two alphas differ by the
-    solvers' stopping rounding, far below it).  Bisection stops anywhere in its
+    """Every alpha mode with 4- and 2-byte storage on D1Q3 and D2Q9 (whose
+    kernels update four tiles per workgroup; general and grouped-row loads)
+    and D3Q27, on a state with near- and far-from-equilibrium sites
+    (alpha_* < 2 and the rare tier on some): one step against the oracle
+    from the decoded stored state to one output rounding (the two alphas
+    differ by the solvers' stopping rounding, far below it).  Bisection stops anywhere in its
     window -tol <= G <= 0, which near equilibrium (G' ~ 1e-8) spans alphas
     1e-5 apart, so the two sides often stop at different midpoints: where
     the two alphas differ, the GPU's is checked against the window with the
     oracle's G, and the populations of the other sites (at least half) are
     compared."""
-    D = 3 if shape[2] > 1 else 2
+    D = 3 if shape[2] > 1 else (2 if shape[1] > 1 else 1)
     N = int(np.prod(shape))
     W1 = H.textbook_weights(D)
     near = _random_state(D, N, seed=780 + len(storage) + len(mode), eps=0.02, tilt=0.05)
