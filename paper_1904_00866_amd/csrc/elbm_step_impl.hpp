@@ -398,41 +398,70 @@ struct Site {
 //   x_i = f_i / f^eq_i - 1 = (s_i - s^eq_i) / (rho_ref + s^eq_i),
 //   f^eq_i = W_i (rho_ref + s^eq_i);
 // the collision (Eq. (1)) is s~_i = s_i + alpha beta (s^eq_i - s_i).
-template <int D, class S>
-struct SiteDev {
+// The site arithmetic A of the deviation form: FP32 (the mixed policy) or
+// FP64 (the closed form's common tier on FP16 deviation storage with FP64
+// site arithmetic).  Its reciprocals and square roots: the hardware
+// estimates, refined by one Newton step where noted (FP32), or the
+// refined estimates of rcp_n / sqrt_n (FP64).
+template <class A>
+__device__ __forceinline__ A rcp_a(A y) {
+  if constexpr (std::is_same<A, float>::value) {
+    const float r0 = __builtin_amdgcn_rcpf(y);
+    return fmaf(r0, fmaf(-y, r0, 1.0f), r0);
+  } else {
+    return rcp_n<A>(y);
+  }
+}
+template <class A>
+__device__ __forceinline__ A rcp_hw(A y) {  // FP32: the estimate alone (1 ulp)
+  if constexpr (std::is_same<A, float>::value) return __builtin_amdgcn_rcpf(y);
+  else return rcp_n<A>(y);
+}
+template <class A>
+__device__ __forceinline__ A sqrt_hw(A y) {  // FP32: the estimate alone (1 ulp)
+  if constexpr (std::is_same<A, float>::value) return __builtin_amdgcn_sqrtf(y);
+  else return sqrt_n<A>(y);
+}
+
+template <int D, class S, class A = float>
+struct SiteDevT {
   using L = Lattice<D>;
   using T = typename S::T;
   using Real = double;  // arithmetic of the alpha evaluation
+  using Arith = A;      // arithmetic of the deviations
   static constexpr int Q = L::Q;
   static constexpr int kDim = D;
   static constexpr bool kZFactor = false;  // f^eq_i comes from s^eq_i
   static constexpr bool kSumsK1 = true;     // sums_k1() below
+  // the collision takes s_i - s^eq_i as sums_k1 formed them where that costs
+  // fewer registers than the factors s^eq_i is recomputed from
+  static constexpr bool kKeepD = std::is_same<A, float>::value || Q <= 9;
   typename Kept<S>::type raw[Q];
-  float r, dr, rho32;  // rho_ref, rho - rho_ref, rho
+  A r, dr, rho32;  // rho_ref, rho - rho_ref, rho
   double rho, u[3];    // rho and u widened (alpha's guard, diagnostics)
   // s^eq_i = dr + rho Dl_i with Dl_i = (1 + a)(1 + dl_z(dz)) - 1,
   // a = (1 + dl_x(dx)) (1 + dl_y(dy)) - 1, formed as one multiply-add
   // s^eq_i = seqA + seqB dl_z(dz) from seqA = dr + rho a and seqB = rho (1 + a)
-  float seqA[3][3], seqB[3][3];
-  float dlz[3];        // dl_z(dz)
+  A seqA[3][3], seqB[3][3];
+  A dlz[3];        // dl_z(dz)
   // 1 / (rho_ref + s^eq_i) = W_i / f^eq_i = rxy[dx][dy] rlz[dz]: with
   // rho_ref + s^eq_i = rho prod_a (1 + dl_a), the reciprocals of the nine
   // per-axis factors (and 1/rho) give it with one product per direction
-  float rxy[3][3];     // 1 / (rho (1 + dl_x(dx)) (1 + dl_y(dy)))
-  float rlz[3];        // 1 / (1 + dl_z(dz))
-  float dd[Q];         // s_i - s^eq_i as sums_k1 formed them, for the collision
+  A rxy[3][3];     // 1 / (rho (1 + dl_x(dx)) (1 + dl_y(dy)))
+  A rlz[3];        // 1 / (1 + dl_z(dz))
+  A dd[Q];         // s_i - s^eq_i as sums_k1 formed them (kKeepD)
   const T* src;
   uint32_t site;
   const SimDesc* desc;
   Where w;  // filled by locate() before a rare-path loop
 
   // s_i from the kept value (FP32 storage holds f_i: one rounding)
-  __device__ __forceinline__ float s(int i) const {
-    if constexpr (S::dev) return raw[i];
-    else return fmaf(raw[i], float(L::invW(i)), -r);
+  __device__ __forceinline__ A s(int i) const {
+    if constexpr (S::dev) return A(raw[i]);
+    else return fma(A(raw[i]), A(L::invW(i)), -r);
   }
   struct Pass {
-    float dlz[3], rlz[3];
+    A dlz[3], rlz[3];
   };
   __device__ __forceinline__ Pass pass() const {
     Pass p;
@@ -454,69 +483,84 @@ struct SiteDev {
     }
     return p;
   }
-  __device__ __forceinline__ float seq(int i, const Pass& p) const {
-    const float A = seqA[L::dg(i, 0)][L::dg(i, 1)];
-    return D > 2 ? fmaf(seqB[L::dg(i, 0)][L::dg(i, 1)], p.dlz[L::dg(i, 2)], A) : A;
+  __device__ __forceinline__ A seq(int i, const Pass& p) const {
+    const A Av = seqA[L::dg(i, 0)][L::dg(i, 1)];
+    return D > 2 ? fma(seqB[L::dg(i, 0)][L::dg(i, 1)], p.dlz[L::dg(i, 2)], Av) : Av;
   }
   __device__ __forceinline__ double fe(int i, const Pass& p) const {
-    return double(float(L::W(i)) * (r + seq(i, p)));
+    return double(A(L::W(i)) * (r + seq(i, p)));
   }
-  // x_i = (s_i - s^eq_i) / (rho_ref + s^eq_i) to FP32 relative accuracy
-  // (a few roundings of the reciprocal factors): its absolute error is that
-  // of s_i - s^eq_i, O(|u|) times FP32 rounding
-  __device__ __forceinline__ float rfac(int i, const Pass& p) const {
-    const float R = rxy[L::dg(i, 0)][L::dg(i, 1)];
+  // x_i = (s_i - s^eq_i) / (rho_ref + s^eq_i) to the arithmetic's relative
+  // accuracy (a few roundings of the reciprocal factors): its absolute error
+  // is that of s_i - s^eq_i, O(|u|) times the rounding
+  __device__ __forceinline__ A rfac(int i, const Pass& p) const {
+    const A R = rxy[L::dg(i, 0)][L::dg(i, 1)];
     return D > 2 ? R * p.rlz[L::dg(i, 2)] : R;
   }
   __device__ __forceinline__ double x(int i, const Pass& p) const {
     return double((s(i) - seq(i, p)) * rfac(i, p));
   }
   // The common-tier sums to their first terms, E = sum_i f^eq_i x_i^2 / 2
-  // and O = sum_i f^eq_i x_i^3 / 6, in FP32, and max_i |x_i|: for results
-  // stored in 2 bytes (the FP32 rounding moves alpha by about 2^-24 max|x_i|,
-  // far below what 11 stored bits resolve).  With d_i = s_i - s^eq_i,
-  // f^eq_i x_i = W_i d_i, so E and O are W-weighted sums of d_i x_i and
-  // d_i x_i^2, summed per weight class (W_i = 4^z / 6^D, z the number of
-  // zero components of c_i) and weighted once at the end.
-  __device__ __forceinline__ void sums_k1(const Pass& p, float& sE, float& sO, float& xabs) {
-    float e[D + 1], o[D + 1], xm = 0.0f;
+  // and O = sum_i f^eq_i x_i^3 / 6, and max_i |x_i|, for results stored in
+  // 2 bytes (the closed form's one-term tier).  In FP32 the rounding moves
+  // alpha by about 2^-24 max|x_i|, far below what 11 stored bits resolve.
+  // With d_i = s_i - s^eq_i, f^eq_i x_i = W_i d_i, so E and O are W-weighted
+  // sums of d_i x_i and d_i x_i^2, summed per weight class (W_i = 4^z / 6^D,
+  // z the number of zero components of c_i) and weighted once at the end.
+  __device__ __forceinline__ void sums_k1(const Pass& p, A& sE, A& sO, A& xabs) {
+    A e[D + 1], o[D + 1], xm = A(0);
 #pragma unroll
-    for (int z = 0; z <= D; ++z) e[z] = o[z] = 0.0f;
+    for (int z = 0; z <= D; ++z) e[z] = o[z] = A(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float di = s(i) - seq(i, p);
-      dd[i] = di;
-      const float xi = di * rfac(i, p);
-      const float t = di * xi;
+      const A di = s(i) - seq(i, p);
+      if constexpr (kKeepD) dd[i] = di;
+      const A xi = di * rfac(i, p);
+      const A t = di * xi;
       const int z = L::nzero(i);
       e[z] += t;
-      o[z] = fmaf(t, xi, o[z]);
-      xm = fmaxf(xm, fabsf(xi));
+      o[z] = fma(t, xi, o[z]);
+      xm = fmax(xm, fabs(xi));
       sched_group(i);
     }
-    float E = 0.0f, O = 0.0f;
+    A E = A(0), O = A(0);
 #pragma unroll
     for (int z = 0; z <= D; ++z) {
-      const float wz = float(double(1 << (2 * z)) / L::den());
-      E = fmaf(wz, e[z], E);
-      O = fmaf(wz, o[z], O);
+      const A wz = A(double(1 << (2 * z)) / L::den());
+      E = fma(wz, e[z], E);
+      O = fma(wz, o[z], O);
     }
-    sE = 0.5f * E;
-    sO = O * float(1.0 / 6.0);
+    sE = A(0.5) * E;
+    sO = O * A(1.0 / 6.0);
     xabs = xm;
+  }
+  // s_i - s^eq_i for the collision
+  __device__ __forceinline__ A dev(int i, const Pass& p) const {
+    if constexpr (kKeepD) return dd[i];
+    else return s(i) - seq(i, p);
   }
   // the stored value of s~_i.  FP32 storage holds f~_i = W_i (rho_ref + s~_i),
   // rounded once from W_i = wh + wl (wl: the residual of W_i's FP32
   // rounding): with the FP32 weight alone every step would scale f_i by
   // float(W_i) / W_i, a bias that adds up (the read divides by 1 / W_i, which
-  // is exact).
+  // is exact).  An FP64 deviation goes to FP16 through FP32 (two roundings
+  // to nearest even; gfx950 has no FP64 -> FP16 conversion, and allowed to
+  // merge the two the compiler would expand one into integer arithmetic).
   __host__ __device__ static constexpr float w_lo(double W) { return float(W - double(float(W))); }
   __device__ __forceinline__ static T enc_f(float wh, float wl, float rr, float sn) {
     return T(fmaf(wh, rr, fmaf(wh, sn, wl * (rr + sn))));
   }
-  __device__ __forceinline__ T enc(int i, float sn) const {
-    if constexpr (S::dev) return T(sn);
-    else return enc_f(float(L::W(i)), w_lo(L::W(i)), r, sn);
+  __device__ __forceinline__ T enc(int i, A sn) const {
+    if constexpr (std::is_same<A, double>::value) {
+      static_assert(S::dev, "FP64 deviation arithmetic is built for deviation storage");
+      float h = float(sn);
+      asm volatile("" : "+v"(h));
+      return T(h);
+    } else if constexpr (S::dev) {
+      return T(sn);
+    } else {
+      return enc_f(float(L::W(i)), w_lo(L::W(i)), r, sn);
+    }
   }
 
   // H(f^eq) / rho, as for the FP64 site
@@ -556,8 +600,8 @@ struct SiteDev {
     if constexpr (S::dev) si = float(gv);
     else si = fmaf(float(gv), invweight_of(i), -r);
     // the selections multiply by 0 and 1 and add zeros: exact
-    const float A = sel9(seqA, dx, dy);
-    seqi = D > 2 ? fmaf(sel9(seqB, dx, dy), sel3(dlz, dz), A) : A;
+    const float sa = sel9(seqA, dx, dy);
+    seqi = D > 2 ? fmaf(sel9(seqB, dx, dy), sel3(dlz, dz), sa) : sa;
   }
   __device__ __forceinline__ void xfe(int i, double& xi, double& fi, double* = nullptr) const {
     float si, seqi;
@@ -566,6 +610,8 @@ struct SiteDev {
     fi = double(weight_of(i) * (r + seqi));
   }
 };
+template <int D, class S>
+using SiteDev = SiteDevT<D, S, float>;
 
 // S(a) = sum_i f^eq_i phi((1 - a) x_i); G(a) = H(f*(a)) - H(f) = S(a) - D.
 template <class V, class R>
@@ -804,31 +850,31 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
       sizeof(typename V::T) == 2 && std::is_same<R, double>::value && MODE == kClosed;
   constexpr bool kK1 = kS16 && V::kSumsK1 && !kXmax;
   if constexpr (kK1 && MODE == kClosed && PHASE == kPhaseCommon) {
-    // The common phase of the closed form on them, in FP32: alpha_* = 2
-    // (max|x_i| <= 0.025 < 1), D = E - O, G(2) = 2 O, D*(2) = E + O, and
-    // Eq. (9) gives alpha = 2 - 2 O / (E + O) where G(2) > 0.  The quotient
-    // (below |x| / 3) carries FP32 rounding; 2 minus it is formed in FP64.
-    float E, O, xm;
+    // The common phase of the closed form on them, in the deviation site's
+    // arithmetic A: alpha_* = 2 (max|x_i| <= 0.025 < 1), D = E - O,
+    // G(2) = 2 O, D*(2) = E + O, and Eq. (9) gives alpha = 2 - 2 O / (E + O)
+    // where G(2) > 0.  The quotient (below |x| / 3) carries A's rounding;
+    // 2 minus it is formed in FP64.
+    using A = typename V::Arith;
+    A E, O, xm;
     v.sums_k1(v.pass(), E, O, xm);
     o.iters = 0;
     o.astar_lt2 = o.fallback = false;
-    if (!(xm <= float(Base<R>::thrM))) {
+    if (!(xm <= A(Base<R>::thrM))) {
       o.deferred = true;
       o.alpha = R(2);
       o.D = R(0);
       o.accepted2 = o.guard = false;
       return o;
     }
-    const float Dv = E - O;
+    const A Dv = E - O;
     o.D = R(Dv);
-    o.guard = !(Dv > float(Prec<R>::guard) * v.rho32);
-    o.accepted2 = o.guard || !(O > 0.0f);
+    o.guard = !(Dv > A(Prec<R>::guard) * v.rho32);
+    o.accepted2 = o.guard || !(O > A(0));
     o.alpha = R(2);
     if (!o.accepted2) {
-      const float Ds = E + O;
-      const float r0 = __builtin_amdgcn_rcpf(Ds);
-      const float r = fmaf(r0, fmaf(-Ds, r0, 1.0f), r0);
-      o.alpha = R(2) - R(fminf(2.0f * O * r, 1.0f));  // clamped to [1, 2]
+      const A r = rcp_a(E + O);
+      o.alpha = R(2) - R(fmin(A(2) * O * r, A(1)));  // clamped to [1, 2]
       o.iters = 1;
     }
     return o;
@@ -848,7 +894,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
   const R thrC = kS16 ? Base<R>::thrM : Base<R>::thr;
   R xmax = R(-1), xabs = R(0), sE = R(0), sO = R(0);
   if constexpr (PHASE != kPhaseRare && kK1) {
-    float E, O, xm;
+    typename V::Arith E, O, xm;
     v.sums_k1(v.pass(), E, O, xm);
     sE = E;
     sO = O;
@@ -1398,49 +1444,55 @@ __device__ __forceinline__ void moments_of(const G& g, R& rho, R (&j)[3]) {
 // 6^-D is applied once, in two FP32 parts: its FP32 rounding alone would
 // scale every moment by the same wrong factor at every step, a bias that
 // the collision hands on to the state.
-template <int D, class G>
-__device__ __forceinline__ void moments_w4(const G& s, float& dr, float (&j)[3]) {
+template <int D, class A, class G>
+__device__ __forceinline__ void moments_w4(const G& s, A& dr, A (&j)[3]) {
   constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
-  float ax[3][3], bx[3][3];  // [c_y][c_z]
+  A ax[3][3], bx[3][3];  // [c_y][c_z]
 #pragma unroll
   for (int dz = 0; dz < NZ; ++dz)
 #pragma unroll
     for (int dy = 0; dy < NY; ++dy) {
       const int i0 = 9 * dz + 3 * dy;
-      const float s0 = s(i0), sp = s(i0 + 1), sm = s(i0 + 2);
-      ax[dy][dz] = fmaf(4.0f, s0, sp + sm);
+      const A s0 = s(i0), sp = s(i0 + 1), sm = s(i0 + 2);
+      ax[dy][dz] = fma(A(4), s0, sp + sm);
       bx[dy][dz] = sp - sm;
     }
-  float ay[3], by[3], cy[3];  // [c_z]
+  A ay[3], by[3], cy[3];  // [c_z]
 #pragma unroll
   for (int dz = 0; dz < NZ; ++dz) {
     if constexpr (D > 1) {
-      ay[dz] = fmaf(4.0f, ax[0][dz], ax[1][dz] + ax[2][dz]);
-      by[dz] = fmaf(4.0f, bx[0][dz], bx[1][dz] + bx[2][dz]);
+      ay[dz] = fma(A(4), ax[0][dz], ax[1][dz] + ax[2][dz]);
+      by[dz] = fma(A(4), bx[0][dz], bx[1][dz] + bx[2][dz]);
       cy[dz] = ax[1][dz] - ax[2][dz];
     } else {
       ay[dz] = ax[0][dz];
       by[dz] = bx[0][dz];
-      cy[dz] = 0.0f;
+      cy[dz] = A(0);
     }
   }
-  float S, J[3];
+  A S, J[3];
   if constexpr (D > 2) {
-    S = fmaf(4.0f, ay[0], ay[1] + ay[2]);
-    J[0] = fmaf(4.0f, by[0], by[1] + by[2]);
-    J[1] = fmaf(4.0f, cy[0], cy[1] + cy[2]);
+    S = fma(A(4), ay[0], ay[1] + ay[2]);
+    J[0] = fma(A(4), by[0], by[1] + by[2]);
+    J[1] = fma(A(4), cy[0], cy[1] + cy[2]);
     J[2] = ay[1] - ay[2];
   } else {
     S = ay[0];
     J[0] = by[0];
     J[1] = cy[0];
-    J[2] = 0.0f;
+    J[2] = A(0);
   }
   constexpr double c = 1.0 / Lattice<D>::den();
-  constexpr float ch = float(c), cl = float(c - double(float(c)));
-  dr = fmaf(ch, S, cl * S);
+  if constexpr (std::is_same<A, float>::value) {
+    constexpr float ch = float(c), cl = float(c - double(float(c)));
+    dr = fmaf(ch, S, cl * S);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) j[a] = a < D ? fmaf(ch, J[a], cl * J[a]) : 0.0f;
+    for (int a = 0; a < 3; ++a) j[a] = a < D ? fmaf(ch, J[a], cl * J[a]) : 0.0f;
+  } else {
+    dr = A(c) * S;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) j[a] = a < D ? A(c) * J[a] : A(0);
+  }
 }
 
 template <int D, class S, class R>
@@ -1478,37 +1530,36 @@ struct Mixed {};
 template <class P>
 constexpr bool kIsMixed = std::is_same<P, Mixed>::value;
 
-// The mixed policy's preparation (SiteDev): moments of the deviations and
-// the per-axis deviations dl of the equilibrium factors.
-template <int D, class S>
-__device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc& d,
+// The preparation of the deviation site (SiteDevT): moments of the
+// deviations and the per-axis deviations dl of the equilibrium factors, in
+// the site's arithmetic A.
+template <int D, class S, class A>
+__device__ __forceinline__ void site_prepare_dev(SiteDevT<D, S, A>& v, const SimDesc& d,
                                                  const typename S::T* src, uint32_t sl,
                                                  double (&j)[3]) {
-  using L = Lattice<D>;
   v.src = src;
   v.site = sl;
   v.desc = &d;
-  v.r = float(d.rho_ref);
-  float dr, j32[3];
-  moments_w4<D>([&](int i) { return v.s(i); }, dr, j32);
-  const float rho32 = v.r + dr;
-  // FP32 arithmetic: the hardware reciprocal refined by one Newton step
-  // (e = 1 - rho r, r <- r + r e) and the hardware square root (1 ulp)
-  // instead of the correctly rounded library division and square root
-  const float irho0 = __builtin_amdgcn_rcpf(rho32);
-  const float irho = fmaf(irho0, fmaf(-rho32, irho0, 1.0f), irho0);
-  float dl[3][3];
+  v.r = A(d.rho_ref);
+  A dr, jA[3];
+  moments_w4<D>([&](int i) { return v.s(i); }, dr, jA);
+  const A rho = v.r + dr;
+  // FP32: the hardware reciprocal refined by one Newton step and the
+  // hardware square root (1 ulp) instead of the correctly rounded library
+  // division and square root; FP64: refined estimates
+  const A irho = rcp_a(rho);
+  A dl[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
-      const float ua = j32[a] * irho, t = 3.0f * ua * ua;
-      const float q = t * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_sqrtf(1.0f + t));
+      const A ua = jA[a] * irho, t = A(3) * ua * ua;
+      const A q = t * rcp_hw(A(1) + sqrt_hw(A(1) + t));
       dl[a][0] = -q;
-      dl[a][1] = fmaf(3.0f, ua, 2.0f * q);
-      dl[a][2] = fmaf(-3.0f, ua, 2.0f * q);
+      dl[a][1] = fma(A(3), ua, A(2) * q);
+      dl[a][2] = fma(A(-3), ua, A(2) * q);
       v.u[a] = ua;
     } else {
-      dl[a][0] = dl[a][1] = dl[a][2] = 0.0f;
+      dl[a][0] = dl[a][1] = dl[a][2] = A(0);
       v.u[a] = 0.0;
     }
   }
@@ -1516,51 +1567,51 @@ __device__ __forceinline__ void site_prepare_dev(SiteDev<D, S>& v, const SimDesc
   // cofactor C_c (product of the other two factors of the axis) and
   // P_a = F_0 F_+ F_- = F_c C_c, 1 / F_c = C_c / P_a.  The x and y axes share
   // one reciprocal, 1 / (rho P_x P_y), times 1/rho's; z has its own.  Each
-  // quotient carries a few FP32 roundings (the hardware reciprocal is good to
-  // 1 ulp).
-  float F[3][3], C[3][3], P[3];
+  // quotient carries a few roundings of the arithmetic (the FP32 hardware
+  // reciprocal is good to 1 ulp).
+  A F[3][3], C[3][3], P[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (a < D) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[a][c] = 1.0f + dl[a][c];
+      for (int c = 0; c < 3; ++c) F[a][c] = A(1) + dl[a][c];
       C[a][0] = F[a][1] * F[a][2];
       C[a][1] = F[a][0] * F[a][2];
       C[a][2] = F[a][0] * F[a][1];
       P[a] = F[a][0] * C[a][0];
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) F[a][c] = C[a][c] = 1.0f;
-      P[a] = 1.0f;
+      for (int c = 0; c < 3; ++c) F[a][c] = C[a][c] = A(1);
+      P[a] = A(1);
     }
   }
-  const float Rxy = irho * __builtin_amdgcn_rcpf(D > 1 ? P[0] * P[1] : P[0]);
+  const A Rxy = irho * rcp_hw(D > 1 ? P[0] * P[1] : P[0]);
   // s^eq_i = dr + rho (F_x F_y F_z - 1), expanded so that no term cancels:
   // seqA = dr + rho (F_x F_y - 1) = (dr + rho dl_x) + (rho dl_y) F_x and
   // seqB = rho F_x F_y, then s^eq_i = seqA + seqB dl_z
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float Rx = Rxy * C[0][a];
-    const float Ax = fmaf(rho32, dl[0][a], dr);
-    const float RFx = rho32 * F[0][a];
+    const A Rx = Rxy * C[0][a];
+    const A Ax = fma(rho, dl[0][a], dr);
+    const A RFx = rho * F[0][a];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      v.seqA[a][b] = D > 1 ? fmaf(rho32 * dl[1][b], F[0][a], Ax) : Ax;
+      v.seqA[a][b] = D > 1 ? fma(rho * dl[1][b], F[0][a], Ax) : Ax;
       v.seqB[a][b] = D > 1 ? RFx * F[1][b] : RFx;
       v.rxy[a][b] = D > 1 ? Rx * C[1][b] : Rx;
     }
   }
-  const float Rz = D > 2 ? __builtin_amdgcn_rcpf(P[2]) : 1.0f;
+  const A Rz = D > 2 ? rcp_hw(P[2]) : A(1);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     v.dlz[k] = dl[2][k];
     v.rlz[k] = Rz * C[2][k];
   }
   v.dr = dr;
-  v.rho32 = rho32;
-  v.rho = rho32;
+  v.rho32 = rho;
+  v.rho = rho;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) j[a] = j32[a];
+  for (int a = 0; a < 3; ++a) j[a] = jA[a];
 }
 
 // Count predicates of one site as bits kCnt*: they are turned into
@@ -1619,9 +1670,10 @@ __device__ __forceinline__ uint32_t record_site(const SimDesc& d, uint32_t s, bo
   return flags;
 }
 
-// The mixed policy's site update (closed form): FP32 arithmetic on the
-// deviations (SiteDev), the entropy differences and alpha in FP64.
-template <int D, class S, int MODE, bool SUMS, int PHASE>
+// The site update on the deviations (SiteDevT) in the arithmetic A: FP32
+// (the mixed policy, every mode; the entropy differences and alpha in
+// FP64), or FP64 (the closed form's common phase on FP16 deviation storage).
+template <int D, class S, class A, int MODE, bool SUMS, int PHASE>
 __device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
                                                 const typename S::T* __restrict__ src,
                                                 typename S::T* __restrict__ dst, uint32_t s,
@@ -1633,28 +1685,26 @@ __device__ __forceinline__ SiteOut site_update_dev(const SimDesc& d,
   using T = typename S::T;
   constexpr uint32_t es = sizeof(T);
   const uint32_t sl = live ? s : 0u;
-  SiteDev<D, S> v;
+  SiteDevT<D, S, A> v;
 #pragma unroll
   for (int i = 0; i < Q; ++i) v.raw[i] = Codec<S, double>::keep(from_slot<typename S::T>(raw[i]));
   double j[3];
   site_prepare_dev(v, d, src, sl, j);
   const AlphaOut<double> ao = choose_alpha<MODE, PHASE>(v, d);
   if (PHASE == kPhaseCommon && ao.deferred) return SiteOut{true, 0u};
-  const float ab = float(ao.alpha * d.beta);
+  const A ab = A(ao.alpha * d.beta);
   const auto P = v.pass_opaque();
-  float tmin = INFINITY;  // min of f~_i / W_i: its sign is that of f~_i
+  A tmin = A(INFINITY);  // min of f~_i / W_i: its sign is that of f~_i
   const uint32_t lo = (s & 63u) * es;
   const gaddr blk = block_base<Q>(dst, s);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float si = v.s(i);
-    // the common phase of the closed form on 2-byte storage reuses the
-    // deviations s_i - s^eq_i of its sums (sums_k1): keeping those 27 values
-    // live costs fewer registers than keeping the factors s^eq_i is
-    // recomputed from
+    const A si = v.s(i);
+    // the common phase of the closed form on 2-byte storage takes the
+    // deviations s_i - s^eq_i from its sums (sums_k1)
     constexpr bool kDD = sizeof(T) == 2 && MODE == kClosed && PHASE == kPhaseCommon;
-    const float sn = kDD ? fmaf(-ab, v.dd[i], si) : fmaf(ab, v.seq(i, P) - si, si);
-    if constexpr (PHASE != kPhaseCommon) tmin = fminf(tmin, v.r + sn);
+    const A sn = kDD ? fma(-ab, v.dev(i, P), si) : fma(ab, v.seq(i, P) - si, si);
+    if constexpr (PHASE != kPhaseCommon) tmin = fmin(tmin, v.r + sn);
     st_nt<T>(blk + i * kLane * es, kLane * es, lo, v.enc(i, sn));
     sched_group(i);
   }
@@ -1756,8 +1806,16 @@ __device__ __forceinline__ SiteOut site_update(const SimDesc& d, const typename 
                                             typename S::T* __restrict__ dst, uint32_t s,
                                             bool live, const Slot<typename S::T> (&raw)[Lattice<D>::Q],
                                             Acc& acc, int diag) {
+  // the closed form's common phase on FP16 deviations with FP64 site
+  // arithmetic, up to nine directions: the deviation site in FP64 (its rare
+  // phase: the FP64 site).  With 27 directions its FP64 state does not fit
+  // the registers of three waves per SIMD, and the FP64 site is faster.
+  constexpr bool kDev64 = std::is_same<AP, double>::value && Codec<S, double>::kF16 &&
+                          MODE == kClosed && PHASE == kPhaseCommon && Lattice<D>::Q <= 9;
   if constexpr (kIsMixed<AP>)
-    return site_update_dev<D, S, MODE, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
+    return site_update_dev<D, S, float, MODE, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
+  else if constexpr (kDev64)
+    return site_update_dev<D, S, double, MODE, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
   else
     return site_update_fp<D, S, MODE, AP, SUMS, PHASE>(d, src, dst, s, live, raw, acc, diag);
 }
