@@ -22,11 +22,13 @@ is needed; its parity with the CPU oracle is established by the GPU tests).
     python experiments.py w5p    the serving stream (64 requests at 20/s) through
                                  a server with 8 slots, first come first served
                                  and with preemption: latency percentiles, MLUPS
-    python experiments.py f3     D3Q19 beside D3Q27: 512^3 FP32 step time and
-                                 HBM roofline fraction of the closed form, LBGK
-                                 and (256^3) Newton; 128^3 Re = 1600 Taylor-Green:
+    python experiments.py f3     D3Q19 beside D3Q27: 512^3 step time and HBM
+                                 roofline fraction of the closed form, LBGK and
+                                 (256^3) Newton; 128^3 Re = 1600 Taylor-Green:
                                  kinetic-energy decay and the share of sites
-                                 with alpha < 2 on both lattices
+                                 with alpha < 2 on both lattices (FP32 storage
+                                 and FP64 arithmetic unless --f3-storage and
+                                 --f3-arith say otherwise)
     python experiments.py f3burg Burg's entropy beside the Boltzmann entropy
                                  (closed form, FP32 storage): step time and HBM
                                  fraction at D3Q27 512^3 and D2Q9 2048^2, Newton
@@ -333,12 +335,14 @@ def w4cmp(ref_path, run_dir):
 
 # --------------------------------------------------------------------- F3 --
 HBM_PEAK_GBS = 8000.0
+ELEM_BYTES = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}
 
 
 def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
-       modes=("closed", "bgk", "newton"), lattices=("d3q19", "d3q27")):
-    out = {"experiment": "f3", "workload": f"3-D Taylor-Green (u0 = 0.05, Re = 1600), FP32 "
-           f"storage, FP64 site arithmetic: step timing at {n}^3 (Newton {newton_n}^3), "
+       modes=("closed", "bgk", "newton"), lattices=("d3q19", "d3q27"), storage="f32",
+       arith="fp64"):
+    out = {"experiment": "f3", "workload": f"3-D Taylor-Green (u0 = 0.05, Re = 1600), {storage} "
+           f"storage, {arith} site arithmetic: step timing at {n}^3 (Newton {newton_n}^3), "
            f"{steps} timed steps after 3 warm-up; limiter statistics at {tgv_n}^3 over "
            f"{tgv_steps} steps", "timing": {}, "tgv": {}}
     if copy_mib:
@@ -358,15 +362,16 @@ def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
             if m not in fields:
                 fields[m] = Wk.taylor_green_3d(m)
             rho, u = fields[m]
-            with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage="f32", mode=mode,
-                                 beta=Wk.tgv3d_beta(m)) as sim:
+            with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage=storage, mode=mode,
+                                 fp64=arith, beta=Wk.tgv3d_beta(m)) as sim:
                 sim.step(3)
                 k = steps if mode != "newton" else 3
                 ms = _timed_steps(sim, k)
-            gbs = 2.0 * Q * 4 * N / (ms * 1e-3) / 1e9
+            b = ELEM_BYTES[storage]
+            gbs = 2.0 * Q * b * N / (ms * 1e-3) / 1e9
             out["timing"][f"{lat}_{mode}"] = {
                 "n": m, "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
-                "algorithmic_gb_per_step": round(2.0 * Q * 4 * N / 1e9, 4),
+                "algorithmic_gb_per_step": round(2.0 * Q * b * N / 1e9, 4),
                 "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
             log(f"f3 {lat} {mode} {m}^3: {out['timing'][f'{lat}_{mode}']}")
             torch.cuda.empty_cache()
@@ -375,7 +380,7 @@ def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
         m = tgv_n
         rho, u = Wk.taylor_green_3d(m)
         rec = []
-        with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage="f32",
+        with elbm.Simulation(lat, m, m, m, rho0=rho, u0=u, storage=storage, fp64=arith,
                              beta=Wk.tgv3d_beta(m), diag=elbm.DIAG_COUNTS) as sim:
             r, v = sim.moments()
             ke0 = _kinetic(r, v)
@@ -517,6 +522,8 @@ def main():
     ap.add_argument("--f3-tgv-steps", type=int, default=2000)
     ap.add_argument("--f3-modes", default="closed,bgk,newton")
     ap.add_argument("--f3-lattices", default="d3q19,d3q27")
+    ap.add_argument("--f3-storage", default="f32", choices=sorted(ELEM_BYTES))
+    ap.add_argument("--f3-arith", default="fp64", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--f3burg-cases", default="",
                     help="comma list of lattice_mode_entropy cases (default: all)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -539,7 +546,8 @@ def main():
                "f3": lambda: f3(n=args.f3_n, steps=args.f3_steps,
                                 tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
                                 modes=tuple(args.f3_modes.split(",")),
-                                lattices=tuple(args.f3_lattices.split(",")))
+                                lattices=tuple(args.f3_lattices.split(",")),
+                                storage=args.f3_storage, arith=args.f3_arith)
                }.get(w, lambda: w2(args.w2_steps))()
         res["wall_s"] = round(time.time() - t0, 1)
         print(json.dumps(res), flush=True)

@@ -437,7 +437,7 @@ struct SiteDevT {
   // fewer registers than the factors s^eq_i is recomputed from
   static constexpr bool kKeepD = std::is_same<A, float>::value || Q <= 9;
   typename Kept<S>::type raw[Q];
-  A r, dr, rho32;  // rho_ref, rho - rho_ref, rho
+  A r, dr, rhoA;  // rho_ref, rho - rho_ref, rho (in the arithmetic A)
   double rho, u[3];    // rho and u widened (alpha's guard, diagnostics)
   // s^eq_i = dr + rho Dl_i with Dl_i = (1 + a)(1 + dl_z(dz)) - 1,
   // a = (1 + dl_x(dx)) (1 + dl_y(dy)) - 1, formed as one multiply-add
@@ -869,7 +869,7 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
     }
     const A Dv = E - O;
     o.D = R(Dv);
-    o.guard = !(Dv > A(Prec<R>::guard) * v.rho32);
+    o.guard = !(Dv > A(Prec<R>::guard) * v.rhoA);
     o.accepted2 = o.guard || !(O > A(0));
     o.alpha = R(2);
     if (!o.accepted2) {
@@ -1608,7 +1608,7 @@ __device__ __forceinline__ void site_prepare_dev(SiteDevT<D, S, A>& v, const Sim
     v.rlz[k] = Rz * C[2][k];
   }
   v.dr = dr;
-  v.rho32 = rho;
+  v.rhoA = rho;
   v.rho = rho;
 #pragma unroll
   for (int a = 0; a < 3; ++a) j[a] = jA[a];
@@ -1634,8 +1634,8 @@ __device__ __forceinline__ bool site_finite(const V& v, R alpha) {
 }
 template <int D, class S>
 __device__ __forceinline__ bool site_finite(const SiteDev<D, S>& v, double alpha) {
-  return isfinite(v.rho32 * float(alpha) * float(v.u[0]) * float(v.u[1]) * float(v.u[2]) +
-                  v.rho32);
+  return isfinite(v.rhoA * float(alpha) * float(v.u[0]) * float(v.u[1]) * float(v.u[2]) +
+                  v.rhoA);
 }
 
 template <bool SUMS, class V, class R>
