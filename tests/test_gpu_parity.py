@@ -377,6 +377,12 @@ def test_one_step_modes_reduced_storage_far(gpu, orc, shape, storage, mode):
     W = W1[:, None]
     tol = _storage_rounding(storage, fo, W) + 1e-12 * np.abs(fo)
     ok = np.abs(fg - fo) <= tol
+    if mode == "closed":
+        # 2-byte storage: the common tier (max|x_i| <= 0.025) sums E and O to
+        # their first terms, which moves alpha by at most 5e-6; otherwise the
+        # tiers keep alpha to rounding
+        atol = 5e-6 if storage == "f16dev" else 1e-11
+        assert np.max(np.abs(ag - ao)) <= atol, np.max(np.abs(ag - ao))
     if mode == "bisect":
         same = np.abs(ag - ao) <= 1e-14
         assert same.mean() > 0.5
