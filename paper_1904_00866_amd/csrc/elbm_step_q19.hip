@@ -46,9 +46,15 @@ struct SiteQ19 {
   static constexpr int Q = 19;
   static constexpr int kDim = 3;
   static constexpr bool kZFactor = false;
-  static constexpr bool kSumsK1 = false;
+  // FP16 deviation storage with FP64 arithmetic: the closed form's common
+  // tier takes its first-term sums from the deviations (sums_k1)
+  static constexpr bool kSumsK1 =
+      sizeof(T) == 2 && S::dev && std::is_same<R, double>::value;
+  using Arith = R;
   typename Kept<S>::type raw[Q];  // the loaded populations as kept (Kept<S>)
   R rho, irho, rho_ref;
+  R rhoA;   // rho, for the first-term tier's guard
+  R dd[Q];  // s_i - s^eq_i as sums_k1 formed them, for the collision
   R u[3];
   // f^eq_i = F0[dx][dy] (c_z = 0) or F1[dx][dy] e2[dz] (c_z != 0); the
   // corner entries of F1 (no such direction) are zero.  Since
@@ -93,6 +99,44 @@ struct SiteQ19 {
   __device__ __forceinline__ R x(int i, const Pass& p) const {
     const R rf = fd(opp(L::dg(i, 0)), opp(L::dg(i, 1)), opp(L::dg(i, 2)), p) * kap[L::nnz(i)];
     return fma(g(i), rf, R(-1));
+  }
+  // The closed form's common tier on 2-byte deviation storage: the sums to
+  // their first terms, E = sum_i f^eq_i x_i^2 / 2 and O = sum_i f^eq_i x_i^3 / 6,
+  // and max_i |x_i|.  With the stored deviations s_i = f_i / W_i - rho_ref and
+  // d_i = s_i - s^eq_i, f^eq_i x_i = f_i - f^eq_i = W_i d_i and
+  // x_i = d_i W_i / f^eq_i = d_i (W_i kap[n]) f^eq_{-i}, so E and O are sums
+  // of d_i x_i and d_i x_i^2 per weight class (n nonzero components),
+  // weighted once at the end.
+  __device__ __forceinline__ void sums_k1(const Pass& p, R& sE, R& sO, R& xabs) {
+    static_assert(kSumsK1, "first-term sums on 2-byte deviation storage");
+    R kw[3], e[3], o[3], xm = R(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      kw[n] = R(n == 0 ? 1.0 / 3.0 : n == 1 ? 1.0 / 18.0 : 1.0 / 36.0) * kap[n];
+      e[n] = o[n] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int n = L::nnz(i);
+      const R seq = fma(fe(i, p), R(L::invW(i)), -rho_ref);
+      const R di = widen<R>(raw[i]) - seq;
+      dd[i] = di;
+      const R xi = di * (fd(opp(L::dg(i, 0)), opp(L::dg(i, 1)), opp(L::dg(i, 2)), p) * kw[n]);
+      const R t = di * xi;
+      e[n] += t;
+      o[n] = fma(t, xi, o[n]);
+      xm = fmax(xm, fabs(xi));
+    }
+    R E = R(0), O = R(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const R w = R(n == 0 ? 1.0 / 3.0 : n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+      E = fma(w, e[n], E);
+      O = fma(w, o[n], O);
+    }
+    sE = R(0.5) * E;
+    sO = O * R(1.0 / 6.0);
+    xabs = xm;
   }
 
   __device__ __forceinline__ void fold(const EquilibriumQ19<R>& eq) {
@@ -237,6 +281,7 @@ __device__ __forceinline__ void prepare_q19(SiteQ19<S, R>& v, const SimDesc& d,
   moments_q19(v, rho, j);
   const R irho = rcp_n<R>(rho);
   v.rho = rho;
+  v.rhoA = rho;
   v.irho = irho;
 #pragma unroll
   for (int a = 0; a < 3; ++a) v.u[a] = j[a] * irho;
@@ -303,13 +348,22 @@ __device__ __forceinline__ SiteOut update_q19(const SimDesc& d, const typename S
     const R ab = ao.alpha * beta;
     const auto P = v.pass();
     R ftmin = R(INFINITY);
+    // the common phase of the closed form on 2-byte deviation storage takes
+    // s_i - s^eq_i from its sums (sums_k1): s~_i = s_i - alpha beta d_i
+    constexpr bool kDD = SiteQ19<S, R>::kSumsK1 && MODE == kClosed && PHASE == kPhaseCommon;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const R gi = v.g(i);
-      const R ft = fma(ab, v.fe(i, P) - gi, gi);
-      // common and middle tiers: |x_i| <= 0.025, no negative population
-      if constexpr (PHASE != kPhaseCommon) ftmin = fmin(ftmin, ft);
-      st_nt<T>(blk + i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, R(L19::invW(i)), v.rho_ref));
+      if constexpr (kDD) {
+        float h = float(fma(-ab, v.dd[i], widen<R>(v.raw[i])));
+        asm volatile("" : "+v"(h));  // two roundings, as Codec::enc takes them
+        st_nt<T>(blk + i * kLane * es, kLane * es, lo, T(h));
+      } else {
+        const R gi = v.g(i);
+        const R ft = fma(ab, v.fe(i, P) - gi, gi);
+        // common and middle tiers: |x_i| <= 0.025, no negative population
+        if constexpr (PHASE != kPhaseCommon) ftmin = fmin(ftmin, ft);
+        st_nt<T>(blk + i * kLane * es, kLane * es, lo, Codec<S, R>::enc(ft, R(L19::invW(i)), v.rho_ref));
+      }
     }
     return SiteOut{false, record_site<SUMS>(d, s, live, v, ao, ftmin, j, acc, diag)};
   }
