@@ -827,6 +827,42 @@ def test_full_size_d3q27_sampled(gpu, orc, n, storage):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage,arith", [("f32", "fp64"), ("f16dev", "fp64"),
+                                           ("f16dev", "mixed")])
+def test_full_size_d2q9_4096_sampled(gpu, orc, storage, arith):
+    """The 4096^2 shear layer in the launch configuration of the D2Q9 step
+    kernels' profiles (four tiles per workgroup, grouped row loads): one
+    step after three, checked against the oracle at 2048 sampled sites (the
+    oracle collides the GPU's own decoded pre-state), row ends and the last
+    site included.  One rounding of the output into the storage format;
+    mixed arithmetic adds 2e-6 of the population."""
+    n = 4096
+    beta = Wk.shear_beta(n)
+    rho, u = Wk.shear_layer(n)
+    sim = _sim(gpu, 2, (n, n, 1), rho=rho, u=u, storage=storage, beta=beta, fp64=arith)
+    del rho, u
+    sim.step(3)
+    rng = np.random.default_rng(4096)
+    sites = np.unique(np.concatenate([rng.integers(0, n * n, 2040),
+                                      [0, n - 1, n, 2 * n - 1, n * n - n, n * n - 1]]))
+    pre = sim.gather(sites, 0).cpu().numpy()
+    sim.step(1)
+    post = sim.gather(sites, 1).cpu().numpy()
+    sim.close()
+    cfg = orc.Config(D=2, nx=1, beta=beta)
+    W = H.textbook_weights(2)
+    for k in range(sites.size):
+        ft, _ = orc.collide_site(cfg, pre[:, k])
+        if storage == "f32":
+            tol = 2.0 ** -24 * np.abs(ft) * 1.01
+        else:
+            tol = W * (2.0 ** -11 * np.abs(ft / W - 1.0) * 1.01 + 2.0 ** -24)
+        if arith == "mixed":
+            tol = tol + 2e-6 * np.abs(ft)
+        assert np.all(np.abs(post[:, k] - ft) <= tol), (sites[k], post[:, k], ft)
+    torch.cuda.empty_cache()
+
+
 def test_full_size_d2q9_shear_1024(gpu, orc):
     """The 1024^2 FP32 shear layer (u0 = 0.04, kappa = 80, delta = 0.05,
     Re = 3e4) after 200 steps: one more step over the whole grid against the
