@@ -281,3 +281,31 @@ def test_q19_edge_boxes(gpu, orc):
             fo, _, _ = orc.step(_ocfg(orc, shape, beta=0.95), fo)
         assert np.max(np.abs(sim.populations().cpu().numpy() - fo) / fo) <= 1e-13, shape
         sim.close()
+
+
+@pytest.mark.parametrize("n,storage", [(512, "f32"), (256, "f16dev")])
+def test_q19_full_size_sampled(gpu, orc, n, storage):
+    """The 512^3 Taylor-Green box of the D3Q19 timing (FP32 storage), and
+    256^3 with FP16 deviation storage (the closed form's first-term tier on
+    the stored deviations): one step after three, checked against the
+    oracle's collision of the GPU's decoded pre-state at 2048 sampled sites
+    (row ends and the last site included); one rounding into the storage
+    format."""
+    b = Wk.tgv3d_beta(n)
+    rho, u = Wk.taylor_green_3d(n)
+    sim = _sim(gpu, (n, n, n), rho=rho, u=u, storage=storage, beta=b)
+    del rho, u
+    sim.step(3)
+    rng = np.random.default_rng(519)
+    sites = np.unique(np.concatenate([rng.integers(0, n ** 3, 2040),
+                                      [0, n - 1, n * n - 1, n ** 3 - n, n ** 3 - 1]]))
+    pre = sim.gather(sites, 0).cpu().numpy()
+    sim.step(1)
+    post = sim.gather(sites, 1).cpu().numpy()
+    sim.close()
+    cfg = orc.Config(D=3, nx=1, q=19, beta=b)
+    for k in range(sites.size):
+        ft, _ = orc.collide_site(cfg, pre[:, k])
+        tol = _tol(storage, ft[:, None])[:, 0]
+        assert np.all(np.abs(post[:, k] - ft) <= tol), (sites[k], post[:, k], ft)
+    torch.cuda.empty_cache()
