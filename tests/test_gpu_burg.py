@@ -184,3 +184,28 @@ def test_burg_batch_rules(gpu):
         assert np.array_equal(c1.populations().cpu().numpy(), rc)
     a.close()
     c.close()
+
+
+def test_burg_full_size_sampled(gpu, orc):
+    """The 512^3 D3Q27 Taylor-Green box of the Burg-entropy timing (FP32
+    storage, closed form): one step after three, checked against the
+    oracle's collision of the GPU's decoded pre-state at 2048 sampled sites
+    (row ends and the last site included); one FP32 rounding of the output."""
+    n = 512
+    b = Wk.tgv3d_beta(n)
+    rho, u = Wk.taylor_green_3d(n)
+    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage="f32", beta=b)
+    del rho, u
+    sim.step(3)
+    rng = np.random.default_rng(533)
+    sites = np.unique(np.concatenate([rng.integers(0, n ** 3, 2040),
+                                      [0, n - 1, n * n - 1, n ** 3 - n, n ** 3 - 1]]))
+    pre = sim.gather(sites, 0).cpu().numpy()
+    sim.step(1)
+    post = sim.gather(sites, 1).cpu().numpy()
+    sim.close()
+    cfg = orc.Config(D=3, nx=1, beta=b, entropy="burg")
+    for k in range(sites.size):
+        ft, _ = orc.collide_site(cfg, pre[:, k])
+        assert np.all(np.abs(post[:, k] - ft) <= 2.0 ** -24 * np.abs(ft) * 1.01), sites[k]
+    torch.cuda.empty_cache()
