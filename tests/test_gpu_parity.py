@@ -796,16 +796,18 @@ def test_init_rejects_invalid_fields(gpu):
         gpu.Simulation(2, 16, 16, 1, rho0=rho, u0=u)
 
 
-@pytest.mark.parametrize("n,storage", [(512, "f32"), (256, "f16dev")])
-def test_full_size_d3q27_sampled(gpu, orc, n, storage):
+@pytest.mark.parametrize("n,storage,mode", [(512, "f32", "closed"), (512, "f32", "newton"),
+                                            (256, "f16dev", "closed")])
+def test_full_size_d3q27_sampled(gpu, orc, n, storage, mode):
     """The 512^3 FP32 Taylor-Green box in the benchmark's launch
-    configuration, and the 256^3 box of the precision sweep with FP16
+    configuration (closed form, and the Newton root of Eq. (4) it is
+    compared with), and the 256^3 box of the precision sweep with FP16
     deviation storage: one step checked site by site against the oracle at
     2048 sampled sites (the oracle collides the GPU's own decoded pre-state);
     one rounding of the output into the storage format."""
     b = Wk.tgv3d_beta(n)
     rho, u = Wk.taylor_green_3d(n)
-    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage=storage, beta=b)
+    sim = _sim(gpu, 3, (n, n, n), rho=rho, u=u, storage=storage, beta=b, mode=mode)
     del rho, u
     sim.step(3)
     rng = np.random.default_rng(512)
@@ -814,7 +816,7 @@ def test_full_size_d3q27_sampled(gpu, orc, n, storage):
     pre = sim.gather(sites, 0).cpu().numpy()
     sim.step(1)
     post = sim.gather(sites, 1).cpu().numpy()
-    cfg = orc.Config(D=3, nx=1, beta=b)
+    cfg = orc.Config(D=3, nx=1, beta=b, mode=mode)
     W = H.textbook_weights(3)
     for k in range(sites.size):
         ft, _ = orc.collide_site(cfg, pre[:, k])
