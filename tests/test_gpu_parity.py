@@ -865,6 +865,47 @@ def test_full_size_d2q9_4096_sampled(gpu, orc, storage, arith):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("arith", ["fp64", "mixed"])
+def test_max_sites_d2q9_sampled(gpu, orc, arith):
+    """The largest box the library takes (N < 2^31): D2Q9 46080 x 46603
+    (N = 2,147,466,240; nx a multiple of 1024, so the four-tile grouped row
+    loads), FP16 deviation storage, from a rough seeded field (rho in
+    [0.98, 1.02], each u_a uniform in [-0.05, 0.05]) built on the device.
+    One step after three, checked against the oracle's collision of the
+    GPU's decoded pre-state at 2048 sites: the last rows, the last site and
+    random sites over the whole index range.  One FP16 rounding of the
+    output (mixed arithmetic: plus 2e-6 relative).  About 130 GB of device
+    memory."""
+    nx, ny = 46080, 46603
+    N = nx * ny
+    assert N < 2 ** 31
+    g = torch.Generator(device="cuda").manual_seed(2 ** 31 - 1)
+    rho = torch.rand(N, dtype=torch.float64, device="cuda", generator=g).mul_(0.04).add_(0.98)
+    u = torch.rand(2, N, dtype=torch.float64, device="cuda", generator=g).mul_(0.1).sub_(0.05)
+    sim = _sim(gpu, 2, (nx, ny, 1), rho=rho, u=u, storage="f16dev", beta=0.95, fp64=arith)
+    del rho, u
+    torch.cuda.empty_cache()
+    sim.step(3)
+    rng = np.random.default_rng(2 ** 31)
+    top = np.arange(N - 2 * nx, N, 97)
+    sites = np.unique(np.concatenate([rng.integers(0, N, 2048 - top.size - 3), top,
+                                      [0, nx - 1, N - 1]]))
+    pre = sim.gather(sites, 0).cpu().numpy()
+    sim.step(1)
+    post = sim.gather(sites, 1).cpu().numpy()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    cfg = orc.Config(D=2, nx=1, beta=0.95)
+    W = H.textbook_weights(2)
+    for k in range(sites.size):
+        ft, _ = orc.collide_site(cfg, pre[:, k])
+        tol = W * (2.0 ** -11 * np.abs(ft / W - 1.0) * 1.01 + 2.0 ** -24)
+        if arith == "mixed":
+            tol = tol + 2e-6 * np.abs(ft)
+        assert np.all(np.abs(post[:, k] - ft) <= tol), (sites[k], post[:, k], ft)
+
+
 def test_full_size_d2q9_shear_1024(gpu, orc):
     """The 1024^2 FP32 shear layer (u0 = 0.04, kappa = 80, delta = 0.05,
     Re = 3e4) after 200 steps: one more step over the whole grid against the
