@@ -340,7 +340,7 @@ ELEM_BYTES = {"f64": 8, "f32": 4, "f32dev": 4, "f16dev": 2}
 
 def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
        modes=("closed", "bgk", "newton"), lattices=("d3q19", "d3q27"), storage="f32",
-       arith="fp64"):
+       arith="fp64", late_t=0):
     out = {"experiment": "f3", "workload": f"3-D Taylor-Green (u0 = 0.05, Re = 1600), {storage} "
            f"storage, {arith} site arithmetic: step timing at {n}^3 (Newton {newton_n}^3), "
            f"{steps} timed steps after 3 warm-up; limiter statistics at {tgv_n}^3 over "
@@ -367,12 +367,21 @@ def f3(n=512, newton_n=256, steps=20, tgv_n=128, tgv_steps=2000, copy_mib=0,
                 sim.step(3)
                 k = steps if mode != "newton" else 3
                 ms = _timed_steps(sim, k)
+                ms_late = None
+                if late_t > 3 + 2 * k and mode != "newton":
+                    # the developed flow: as many steps timed again, ending at
+                    # t = late_t
+                    sim.step(late_t - 3 - 2 * k)
+                    ms_late = _timed_steps(sim, k)
             b = ELEM_BYTES[storage]
             gbs = 2.0 * Q * b * N / (ms * 1e-3) / 1e9
             out["timing"][f"{lat}_{mode}"] = {
                 "n": m, "ms_per_step": round(ms, 4), "mlups": round(N / (ms * 1e-3) / 1e6, 1),
                 "algorithmic_gb_per_step": round(2.0 * Q * b * N / 1e9, 4),
                 "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            if ms_late is not None:
+                out["timing"][f"{lat}_{mode}"]["late"] = {"t": late_t,
+                                                         "ms_per_step": round(ms_late, 4)}
             log(f"f3 {lat} {mode} {m}^3: {out['timing'][f'{lat}_{mode}']}")
             torch.cuda.empty_cache()
     fields.clear()
@@ -524,6 +533,8 @@ def main():
     ap.add_argument("--f3-lattices", default="d3q19,d3q27")
     ap.add_argument("--f3-storage", default="f32", choices=sorted(ELEM_BYTES))
     ap.add_argument("--f3-arith", default="fp64", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--f3-late-t", type=int, default=0,
+                    help="also time the steps that end at this t (0: no)")
     ap.add_argument("--f3burg-cases", default="",
                     help="comma list of lattice_mode_entropy cases (default: all)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -547,7 +558,8 @@ def main():
                                 tgv_steps=args.f3_tgv_steps, copy_mib=args.copy_probe_mib,
                                 modes=tuple(args.f3_modes.split(",")),
                                 lattices=tuple(args.f3_lattices.split(",")),
-                                storage=args.f3_storage, arith=args.f3_arith)
+                                storage=args.f3_storage, arith=args.f3_arith,
+                                late_t=args.f3_late_t)
                }.get(w, lambda: w2(args.w2_steps))()
         res["wall_s"] = round(time.time() - t0, 1)
         print(json.dumps(res), flush=True)

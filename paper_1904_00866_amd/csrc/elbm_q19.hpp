@@ -46,12 +46,19 @@ struct LatticeQ19 {
 // X_a = (2 u_a + s_a) / (1 - u_a), exact when the other components vanish;
 // it stops after a step below 1e-9 (FP64) or 3e-4 (FP32), leaving an error
 // of the order of that step's square.  Steps are clamped to [-1/2, 1] so
-// that X stays positive far from the solution.
+// that X stays positive far from the solution.  In FP64, once a first step
+// was small (at most kChordMax), the later steps reuse its inverse Jacobian
+// (chord steps: no new Jacobian, adjugate or determinant).  The Jacobian
+// has moved by O(|d_1|) since, so a chord step leaves an error of about
+// |d_1| times its own size; the iteration stops once that product is at
+// the rounding level of FP64 (2^-53), which at the usual velocities
+// (|d_1| ~ 1e-6 when all three components are nonzero) is the second step.
 template <class R>
 struct EquilibriumQ19 {
   R X[3], Y[3];  // exp(l_a), exp(-l_a)
   R Z9;          // 9 Z(l) at the final X
   static constexpr int kMaxIter = 12;
+  static constexpr double kChordMax = 1e-4;
 
   __device__ __forceinline__ void sums(R (&ch)[3], R (&sh)[3], R& T, R& S2) const {
 #pragma unroll
@@ -73,7 +80,11 @@ struct EquilibriumQ19 {
       Y[a] = de * (de * r);
     }
     const R tol = sizeof(R) == 8 ? R(1e-9) : R(3e-4);
+    constexpr bool kChord = sizeof(R) == 8;
     bool done = false;
+    // the last Jacobian's adjugate and -1/det, and the first step's size
+    R A00 = R(0), A11 = R(0), A22 = R(0), A01 = R(0), A02 = R(0), A12 = R(0), idet = R(0);
+    R d1 = R(1);
     for (int it = 0; it < kMaxIter; ++it) {
       if (!done) {
         R ch[3], sh[3], T, S2;
@@ -86,17 +97,23 @@ struct EquilibriumQ19 {
           m[a] = sh[a] * P[a] * iZ;
           g[a] = m[a] - u[a];
         }
-        const R H00 = fma(ch[0] * P[0], iZ, -m[0] * m[0]);
-        const R H11 = fma(ch[1] * P[1], iZ, -m[1] * m[1]);
-        const R H22 = fma(ch[2] * P[2], iZ, -m[2] * m[2]);
-        const R H01 = fma(sh[0] * sh[1], iZ, -m[0] * m[1]);
-        const R H02 = fma(sh[0] * sh[2], iZ, -m[0] * m[2]);
-        const R H12 = fma(sh[1] * sh[2], iZ, -m[1] * m[2]);
-        // d = -H^-1 g by the adjugate of the symmetric 3 x 3 matrix
-        const R A00 = fma(H11, H22, -H12 * H12), A11 = fma(H00, H22, -H02 * H02);
-        const R A22 = fma(H00, H11, -H01 * H01), A01 = fma(H02, H12, -H01 * H22);
-        const R A02 = fma(H01, H12, -H02 * H11), A12 = fma(H01, H02, -H00 * H12);
-        const R idet = -rcp_n<R>(fma(H00, A00, fma(H01, A01, H02 * A02)));
+        const bool chord = kChord && it > 0 && d1 <= R(kChordMax);
+        if (!chord) {
+          const R H00 = fma(ch[0] * P[0], iZ, -m[0] * m[0]);
+          const R H11 = fma(ch[1] * P[1], iZ, -m[1] * m[1]);
+          const R H22 = fma(ch[2] * P[2], iZ, -m[2] * m[2]);
+          const R H01 = fma(sh[0] * sh[1], iZ, -m[0] * m[1]);
+          const R H02 = fma(sh[0] * sh[2], iZ, -m[0] * m[2]);
+          const R H12 = fma(sh[1] * sh[2], iZ, -m[1] * m[2]);
+          // d = -H^-1 g by the adjugate of the symmetric 3 x 3 matrix
+          A00 = fma(H11, H22, -H12 * H12);
+          A11 = fma(H00, H22, -H02 * H02);
+          A22 = fma(H00, H11, -H01 * H01);
+          A01 = fma(H02, H12, -H01 * H22);
+          A02 = fma(H01, H12, -H02 * H11);
+          A12 = fma(H01, H02, -H00 * H12);
+          idet = -rcp_n<R>(fma(H00, A00, fma(H01, A01, H02 * A02)));
+        }
         R d[3];
         d[0] = fma(A00, g[0], fma(A01, g[1], A02 * g[2])) * idet;
         d[1] = fma(A01, g[0], fma(A11, g[1], A12 * g[2])) * idet;
@@ -109,7 +126,8 @@ struct EquilibriumQ19 {
           X[a] = fma(X[a], d[a], X[a]);
           Y[a] = rcp_n<R>(X[a]);
         }
-        done = !(dmax > tol);
+        if (it == 0) d1 = dmax;
+        done = chord ? !(dmax * d1 > R(0x1p-53)) : !(dmax > tol);
       }
       if (__all(done)) break;
     }
