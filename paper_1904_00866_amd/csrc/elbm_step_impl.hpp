@@ -1028,11 +1028,18 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
     } else if constexpr (MODE == kSecant) {
       if (Gs > R(0)) {
         // alpha^(k+1) = a_* + G(a_*) / (G(a_*) - G(alpha^(k))) (alpha^(k) - a_*),
-        // alpha^(0) = 1, so the first iterate is Eq. (9).
+        // alpha^(0) = 1, so the first iterate is Eq. (9): G(1) = -D needs no
+        // pass.  Later iterates take G from the populations held in
+        // registers (the series form of Newton's passes where every lane's
+        // |(1 - a) x_i| allows it, else the log1p pass).
         R a = R(1);
-        v.w = locate<D>(d, v.site);
         for (int k = 0; k < d.secant_iters; ++k) {
-          const R Ga = S_log(v, a) - Dv;
+          R Ga = -Dv;
+          if (k > 0) {
+            R Sv, dS, sA;
+            S_dS_newton(v, d, a, xabs, Sv, dS, sA);
+            Ga = Sv - Dv;
+          }
           const R an = astar + Gs / (Gs - Ga) * (a - astar);
           iters = k + 1;
           if (an == a) break;
@@ -1041,27 +1048,35 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
         alpha = fmin(fmax(a, R(1)), astar);
       }
     } else if constexpr (MODE == kBisect) {
-      // Eq. (4) on [1, alpha_max]; first midpoint with -tol <= G <= 0.
-      v.w = locate<D>(d, v.site);
-      if (S_log(v, amax) - Dv <= R(0)) {
-        alpha = amax;
-      } else {
-        R lo = R(1), hi = amax;
-        const R tol = (R)d.root_tol;
-        alpha = R(-1);
-        for (int k = 1; k <= d.root_max_iter; ++k) {
-          const R mid = R(0.5) * (lo + hi);
-          const R gm = S_log(v, mid) - Dv;
-          iters = k;
-          if (gm <= R(0) && gm >= -tol) {
-            alpha = mid;
+      // Eq. (4) on [1, alpha_max]; first midpoint with -tol <= G <= 0.  G is
+      // taken as in Newton's passes (series on the register-held
+      // populations where every lane allows it, else the log1p pass).  Pass
+      // 0 asks whether G(alpha_max) <= 0 (then alpha = alpha_max); one call
+      // site, so that the pass is inlined once.
+      R lo = R(1), hi = amax;
+      const R tol = (R)d.root_tol;
+      alpha = R(-1);
+      for (int k = 0; k <= d.root_max_iter; ++k) {
+        const R a = k == 0 ? amax : R(0.5) * (lo + hi);
+        R Sv, dS, sA;
+        S_dS_newton(v, d, a, xabs, Sv, dS, sA);
+        const R g = Sv - Dv;
+        if (k == 0) {
+          if (g <= R(0)) {
+            alpha = amax;
             break;
           }
-          if (gm > R(0)) hi = mid;
-          else lo = mid;
+          continue;
         }
-        if (alpha < R(0)) alpha = lo;
+        iters = k;
+        if (g <= R(0) && g >= -tol) {
+          alpha = a;
+          break;
+        }
+        if (g > R(0)) hi = a;
+        else lo = a;
       }
+      if (alpha < R(0)) alpha = lo;
     } else if constexpr (MODE == kNewton) {
       // Eq. (4) by Newton from alpha_* inside the bracket [1, alpha_max]
       // (from its midpoint when alpha_* = alpha_max, where G' is unbounded).
@@ -1925,8 +1940,10 @@ __device__ __forceinline__ uint32_t site_update_rare(const SimDesc& d,
 // the cache lines at their x-edges, then run on the same XCD and L2.  Each
 // simulation's workgroup count is a multiple of 8 and starts at a multiple
 // of 8.
-// The root solvers and FP64 storage keep the registers they need (Newton
-// with 2- and 4-byte storage: three waves per SIMD).
+// The root solvers and FP64 storage keep the registers they need (Newton,
+// the secant and bisection with 2- and 4-byte storage: three waves per
+// SIMD; their passes over the register-held populations fit without
+// spilling outside the diagnostics-sums variants).
 #ifndef ELBM_NEWTON_WAVES
 #define ELBM_NEWTON_WAVES 3
 #endif
@@ -1943,7 +1960,8 @@ template <class S, int MODE>
 constexpr int step_waves() {
   if (sizeof(typename S::T) == 2 && MODE == kClosed) return 3;
   if (sizeof(typename S::T) <= 4 && (MODE == kClosed || MODE == kBGK)) return ELBM_CLOSED_WAVES;
-  if (sizeof(typename S::T) <= 4 && MODE == kNewton) return ELBM_NEWTON_WAVES;
+  if (sizeof(typename S::T) <= 4 && (MODE == kNewton || MODE == kSecant || MODE == kBisect))
+    return ELBM_NEWTON_WAVES;
   return 1;
 }
 
