@@ -144,12 +144,30 @@ __device__ __forceinline__ double dchi(double y) {
   return y <= -1.0 ? -double(INFINITY) : y / (1.0 + y);
 }
 
-// S(a) = sum_i W_i chi((1 - a) x_i) = H(f*(a)) - H(f^eq).
-template <class L, class S>
-__device__ __forceinline__ double S_chi(const SiteBurg<L, S>& v, double a) {
-  double s = 0.0;
+// chi(y) = sum_{n>=2} (-1)^n y^n / n for |y| <= kChiYmax, through y^11 / 11
+// by Horner's rule: the first omitted term is below 2 y^10 / 12 < 2^-54 of
+// the sum, which is about y^2 / 2 (no cancellation between y and ln(1 + y)).
+constexpr double kChiYmax = 0.025;
+__device__ __forceinline__ double chi_series(double y) {
+  double p = -1.0 / 11.0;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) s += L::W(i) * chi((1.0 - a) * v.x[i]);
+  for (int n = 10; n >= 2; --n) p = fma(p, y, (n % 2 ? -1.0 : 1.0) / n);
+  return y * y * p;
+}
+
+// S(a) = sum_i W_i chi((1 - a) x_i) = H(f*(a)) - H(f^eq): by the series
+// where every lane of the wavefront has |(1 - a) x_i| <= kChiYmax, else by
+// the library log1p.
+template <class L, class S>
+__device__ __forceinline__ double S_chi(const SiteBurg<L, S>& v, double a, double xabs) {
+  double s = 0.0;
+  if (__all(fabs(1.0 - a) * xabs <= kChiYmax)) {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) s = fma(L::W(i), chi_series((1.0 - a) * v.x[i]), s);
+  } else {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) s += L::W(i) * chi((1.0 - a) * v.x[i]);
+  }
   return s;
 }
 
@@ -220,7 +238,7 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
         double a = 1.0;
         if (star2) {
           for (int k = 0; k < d.secant_iters; ++k) {
-            const double Ga = S_chi(v, a) - Dv;
+            const double Ga = S_chi(v, a, xabs) - Dv;
             const double an = astar + Gs / (Gs - Ga) * (a - astar);
             iters = k + 1;
             if (an == a) break;
@@ -238,7 +256,7 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
       alpha = -1.0;
       for (int k = 1; k <= d.root_max_iter; ++k) {
         const double mid = 0.5 * (lo + hi);
-        const double gm = S_chi(v, mid) - Dv;
+        const double gm = S_chi(v, mid, xabs) - Dv;
         iters = k;
         if (gm <= 0.0 && gm >= -tol) {
           alpha = mid;
@@ -257,12 +275,24 @@ __device__ __forceinline__ AlphaOut<double> choose_alpha_burg(SiteBurg<L, S>& v,
 #pragma unroll
       for (int i = 0; i < Q; ++i) sA += L::W(i) * fabs(v.x[i]);
       for (int k = 1; k <= d.root_max_iter; ++k) {
+        // S and S' = -sum_i W_i x_i chi'(y_i), chi'(y) = y / (1 + y): the
+        // series and the refined reciprocal where every lane has
+        // |y_i| <= kChiYmax, else the library forms
         double Sv = 0.0, dS = 0.0;
+        if (__all(fabs(1.0 - a) * xabs <= kChiYmax)) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const double y = (1.0 - a) * v.x[i];
-          Sv += L::W(i) * chi(y);
-          dS -= L::W(i) * v.x[i] * dchi(y);
+          for (int i = 0; i < Q; ++i) {
+            const double y = (1.0 - a) * v.x[i];
+            Sv = fma(L::W(i), chi_series(y), Sv);
+            dS = fma(-L::W(i) * v.x[i], y * rcp_n<double>(1.0 + y), dS);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const double y = (1.0 - a) * v.x[i];
+            Sv += L::W(i) * chi(y);
+            dS -= L::W(i) * v.x[i] * dchi(y);
+          }
         }
         const double gv = Sv - Dv;
         iters = k;
