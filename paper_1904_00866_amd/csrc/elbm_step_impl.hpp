@@ -1030,14 +1030,49 @@ __device__ __forceinline__ AlphaOut<typename V::Real> choose_alpha(V& v, const S
         // alpha^(k+1) = a_* + G(a_*) / (G(a_*) - G(alpha^(k))) (alpha^(k) - a_*),
         // alpha^(0) = 1, so the first iterate is Eq. (9): G(1) = -D needs no
         // pass.  Later iterates take G from the populations held in
-        // registers (the series form of Newton's passes where every lane's
-        // |(1 - a) x_i| allows it, else the log1p pass).
+        // registers: where every active lane is on the common tier and two
+        // or more evaluations follow, from one pass forming the power sums
+        // M_n = sum_i f^eq_i x_i^n, n = 2 .. 2K + 1, which give
+        // S(a) = sum_n (-1)^n (1 - a)^n M_n / (n (n - 1)) truncated where
+        // the tier truncates E and O (the iterates lie in [1, 2], so
+        // |(1 - a) x_i| <= |x_i|); otherwise from Newton's passes (series
+        // where every lane's |(1 - a) x_i| allows it, else log1p).
+        constexpr int KS = Base<R>::K, NP = 2 * KS + 2;
+        const bool poly = PHASE != kPhaseRare && d.secant_iters > 2 && __all(common);
+        R M[NP];
+#pragma unroll
+        for (int n = 0; n < NP; ++n) M[n] = R(0);
+        if (poly) {
+          const auto P = v.pass_opaque();
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const R xi = v.x(i, P);
+            R w = v.fe(i, P) * xi * xi;
+#pragma unroll
+            for (int n = 2; n < NP; ++n) {
+              M[n] += w;
+              if (n + 1 < NP) w *= xi;
+            }
+            sched_group(i);
+          }
+        }
         R a = R(1);
         for (int k = 0; k < d.secant_iters; ++k) {
           R Ga = -Dv;
           if (k > 0) {
-            R Sv, dS, sA;
-            S_dS_newton(v, d, a, xabs, Sv, dS, sA);
+            R Sv = R(0);
+            if (poly) {
+              const R b = R(1) - a;
+              R bn = b * b;
+#pragma unroll
+              for (int n = 2; n < NP; ++n) {
+                Sv = fma(R((n % 2 ? -1.0 : 1.0) / (double(n) * (n - 1))) * bn, M[n], Sv);
+                bn *= b;
+              }
+            } else {
+              R dS, sA;
+              S_dS_newton(v, d, a, xabs, Sv, dS, sA);
+            }
             Ga = Sv - Dv;
           }
           const R an = astar + Gs / (Gs - Ga) * (a - astar);
