@@ -797,11 +797,11 @@ def test_init_rejects_invalid_fields(gpu):
 
 
 @pytest.mark.parametrize("n,storage,mode", [(512, "f32", "closed"), (512, "f32", "newton"),
-                                            (256, "f16dev", "closed")])
+                                            (512, "f32", "secant"), (256, "f16dev", "closed")])
 def test_full_size_d3q27_sampled(gpu, orc, n, storage, mode):
     """The 512^3 FP32 Taylor-Green box in the benchmark's launch
-    configuration (closed form, and the Newton root of Eq. (4) it is
-    compared with), and the 256^3 box of the precision sweep with FP16
+    configuration (closed form, the Newton root of Eq. (4) it is compared
+    with, and the modified secant with three iterates), and the 256^3 box of the precision sweep with FP16
     deviation storage: one step checked site by site against the oracle at
     2048 sampled sites (the oracle collides the GPU's own decoded pre-state);
     one rounding of the output into the storage format."""
