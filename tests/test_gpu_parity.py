@@ -705,6 +705,35 @@ def test_secant_iterates_on_the_gpu(gpu, D):
     assert np.all(np.abs(a4 - an)[inner] < np.abs(ac - an)[inner])
 
 
+@pytest.mark.parametrize("D", [2, 3])
+def test_secant_power_sums_near_equilibrium(gpu, orc, D):
+    """The modified secant with three iterates on states whose every site
+    lies on the common tier (max|x_i| <= 8.5e-3), where its later iterates
+    take S(a) from the power sums of x_i in one pass: one FP64 step against
+    the oracle's secant (log1p evaluation).  Populations to 1e-13; alpha to
+    1e-12 + 10 eps / (2 - alpha): the oracle's log1p form carries about
+    eps |x| of rounding in G, i.e. about eps / (2 - alpha) in alpha."""
+    shape = SHAPES[D]
+    N = int(np.prod(shape))
+    f0 = Wk.random_populations(H.textbook_weights(D), N, 0.003, 4400 + D, tilt=0.001)
+    cfg = _ocfg(orc, D, shape, beta=0.97, mode="secant", secant_iters=3)
+    rho, u = orc.moments(cfg, f0)
+    xmax = max(np.max(np.abs(f0[:, s] / orc.equilibrium(D, rho[s], u[:, s]) - 1.0))
+               for s in range(N))
+    assert xmax <= 8e-3, xmax
+    sim = _sim(gpu, D, shape, f0, storage="f64", beta=0.97, mode="secant", secant_iters=3,
+               diag=gpu.DIAG_ALPHA)
+    sim.step(1)
+    fg = sim.populations().cpu().numpy()
+    ag = sim.alpha_field().cpu().numpy()
+    sim.close()
+    fo, ao, d = orc.step(cfg, f0, want_alpha=True, want_diag=True)
+    assert 0 < d["n_alpha_lt2"] < N
+    assert np.max(np.abs(fg - fo) / np.abs(fo)) <= 1e-13
+    cond = 10.0 * 2.0 ** -52 / np.maximum(2.0 - ao, 1e-300)
+    assert np.all(np.abs(ag - ao) <= 1e-12 + cond), np.max(np.abs(ag - ao))
+
+
 def test_d3q27_multistep_fp64_ragged(gpu, orc):
     shape = (24, 20, 18)
     N = int(np.prod(shape))
